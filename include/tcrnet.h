@@ -1,0 +1,168 @@
+/*
+ * tcrnet -- thresholded all-pairs Levenshtein networks of CDR3-beta strings on
+ * AMD Instinct MI355X (gfx950).
+ *
+ * What is computed (paper: Ehrlich et al., "Large-scale GPU-based network
+ * analysis of the human T-cell receptor repertoire", Methods):
+ *   - "Levenshtein distance", Eq. (levenshtein): unit-cost insertions,
+ *     deletions and substitutions; row/column 0 of the recursion stand for the
+ *     empty prefix.
+ *   - "TCR network": one node per input sequence; nodes i and j are joined iff
+ *     lev(s_i, s_j) <= l_max (here: k).  Equal strings are distinct nodes
+ *     joined by a distance-0 edge.  No self-pairs.
+ *   - "Adjacency matrix": undirected edges, reported once as (i, j), i < j.
+ *   - "Overview of network theory concepts": degree d(u) = sum_v A_uv.
+ *
+ * Conventions for every call:
+ *   - Node ids are 0-based input positions (the paper numbers from 1).
+ *   - Edge lists are arrays of 2*E uint32 values (i0, j0, i1, j1, ...) with
+ *     i < j, sorted lexicographically by (i, j), without duplicates.
+ *   - Degrees are int32, one per node.
+ *   - Sequences are ASCII over the 20 amino-acid letters
+ *     A R N D C Q E G H I L K M F P S T W Y V (paper, Methods, "Combination of
+ *     amino acids"); each has 1..32 residues (one 32-bit bit-vector word).
+ *     Anything else is TCRNET_EINVAL.
+ *   - 0 <= k <= 31.
+ *   - Every call returns a status (TCRNET_OK = 0).  On error, output pointers
+ *     are set to NULL, nothing is returned half-built, and
+ *     tcrnet_last_error() describes the failure (thread-local).
+ *   - Input buffers are borrowed only for the duration of a call and copied.
+ *     Results are owned by the library until the matching *_free call.
+ *   - A context may be used from one thread at a time.  An index may be used
+ *     from several threads (its calls serialize internally where needed).
+ */
+#ifndef TCRNET_H
+#define TCRNET_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(TCRNET_BUILDING)
+#define TCRNET_API __attribute__((visibility("default")))
+#else
+#define TCRNET_API
+#endif
+
+/* ------------------------------------------------------------------ status */
+#define TCRNET_OK 0
+#define TCRNET_EINVAL 1  /* bad argument: NULL pointer, residue outside the
+                            alphabet, length 0 or > 32, k outside [0, 31] */
+#define TCRNET_ENOMEM 2  /* device or host allocation failed, or a request
+                            does not fit the serving memory budget */
+#define TCRNET_EDEVICE 3 /* HIP runtime error (message in tcrnet_last_error) */
+#define TCRNET_ESTATE 4  /* call not valid in the object's current state
+                            (unknown ticket, result already taken, ...) */
+#define TCRNET_ETRUNC 5  /* caller-provided output buffer too small; the
+                            required size is returned, the call may be
+                            repeated with a larger buffer */
+
+#define TCRNET_MAX_LEN 32
+#define TCRNET_MAX_K 31
+
+typedef struct tcrnet_ctx tcrnet_ctx;
+typedef struct tcrnet_graph tcrnet_graph;
+typedef struct tcrnet_index tcrnet_index;
+typedef struct tcrnet_result tcrnet_result;
+
+/* A set of n sequences: n+1 byte offsets into `data` (offsets[0] need not be
+   0; sequence i is data[offsets[i] .. offsets[i+1])).  Host memory. */
+typedef struct {
+  const char* data;
+  const uint64_t* offsets;
+  uint32_t n;
+} tcrnet_seqs;
+
+/* Options; a zero field selects the default.  Pass NULL for all defaults. */
+typedef struct {
+  uint32_t texts_per_item;  /* texts per work item of the pair kernel
+                               (0: autotuned table / 1024) */
+  uint32_t waves_per_simd;  /* resident waves per SIMD of the persistent
+                               pair kernel (0: 8) */
+  uint64_t edge_capacity;   /* initial edge buffer capacity in edges (0: sized
+                               from N); too small only costs one re-run */
+  uint64_t hbm_budget;      /* serving: bytes of device memory that admitted
+                               requests may hold at once (0: 1/4 of free) */
+  uint32_t max_inflight;    /* serving: requests on the device at once (0: 4) */
+  uint32_t flags;           /* TCRNET_F_* */
+} tcrnet_opts;
+
+#define TCRNET_F_NO_AUTOTUNE 1u   /* never consult or run the autotuner */
+#define TCRNET_F_PEQ_LDS 2u       /* keep pattern bit masks in LDS instead of VGPRs */
+
+/* Create a context on HIP device `device` (stream, workspace, options).
+   Fails with TCRNET_EDEVICE if the device is absent or not gfx950. */
+TCRNET_API int32_t tcrnet_ctx_create(int32_t device, const tcrnet_opts* opts, tcrnet_ctx** out);
+TCRNET_API int32_t tcrnet_ctx_destroy(tcrnet_ctx* ctx);
+
+/* Message of the last failed call on this thread ("" if none). */
+TCRNET_API const char* tcrnet_last_error(void);
+/* Static name of a status code. */
+TCRNET_API const char* tcrnet_status_string(int32_t status);
+/* Library version string. */
+TCRNET_API const char* tcrnet_version(void);
+
+/* ------------------------------------------------------------ plain build
+ * The whole network of `seqs` at threshold k (paper, "TCR network" and
+ * "GPU-based network generation": all pairs, thresholded, sparse output).
+ * Inputs are copied to the device once; edges and degrees are copied back.
+ * N = 0 and N = 1 are valid and give E = 0. */
+TCRNET_API int32_t tcrnet_build(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k,
+                                tcrnet_graph** out);
+
+/* Same computation on device-resident input and output, with no host copy
+ * of sequences or results and no device allocation once the context's
+ * workspace has grown to the input size.
+ *   d_data, d_offsets (n+1 entries): device pointers, valid during the call.
+ *   stream: a hipStream_t the work is ordered on (NULL: the context's stream).
+ *   d_pairs: device buffer of 2 * pair_capacity uint32 (edge list as above).
+ *   d_degree: device buffer of n int32.
+ *   *n_edges: receives E.  If E > pair_capacity the call returns
+ *   TCRNET_ETRUNC and only *n_edges is meaningful (d_pairs and d_degree hold
+ *   partial data); repeat the call with pair_capacity >= E.
+ * The call returns after the work completes (it reads the edge count). */
+TCRNET_API int32_t tcrnet_build_device(tcrnet_ctx* ctx, const char* d_data, const uint64_t* d_offsets,
+                                       uint32_t n, int32_t k, void* stream, uint32_t* d_pairs,
+                                       uint64_t pair_capacity, int32_t* d_degree, uint64_t* n_edges);
+
+/* Many independent repertoires (each its own network, own 0-based ids) in
+ * one launch sequence: one persistent pair kernel over all repertoires' work
+ * items, captured in a HIP graph.  outs[r] receives repertoire r's graph. */
+TCRNET_API int32_t tcrnet_build_batch(tcrnet_ctx* ctx, const tcrnet_seqs* reps, uint32_t n_reps,
+                                      int32_t k, tcrnet_graph** outs);
+
+/* Host views of a graph (valid until tcrnet_graph_free). */
+TCRNET_API int32_t tcrnet_graph_edges(const tcrnet_graph* g, const uint32_t** pairs, uint64_t* n_edges);
+TCRNET_API int32_t tcrnet_graph_degree(const tcrnet_graph* g, const int32_t** degree, uint32_t* n);
+/* Counters of the build that made `g`: evaluated (length-compatible) pairs,
+   pair-kernel time in milliseconds (HIP events around the pair kernel on its
+   stream), whole-build time in ms (events around all device work), the
+   number of pipeline launches (more than 1 after an edge-buffer overflow),
+   and the schedule used. */
+typedef struct {
+  uint64_t evaluated_pairs;
+  double pair_kernel_ms;
+  double build_ms;
+  uint32_t pair_launches;
+  uint32_t texts_per_item;
+  uint32_t waves_per_simd;
+  uint32_t peq_lds;
+} tcrnet_build_info;
+TCRNET_API int32_t tcrnet_graph_info(const tcrnet_graph* g, tcrnet_build_info* info);
+/* Counters of the context's most recent build of any kind. */
+TCRNET_API int32_t tcrnet_ctx_last_info(const tcrnet_ctx* ctx, tcrnet_build_info* info);
+TCRNET_API void tcrnet_graph_free(tcrnet_graph* g);
+
+/* --------------------------------------------------------------- autotune
+ * Time candidate pair-kernel schedules (texts per work item, waves per SIMD,
+ * pattern masks in VGPRs or LDS) on `seqs` at threshold k and keep the
+ * fastest in the context for inputs of the same size class and k.  Results
+ * are exact for every candidate; only speed differs. */
+TCRNET_API int32_t tcrnet_autotune(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* TCRNET_H */

@@ -60,6 +60,11 @@ def _bind(lib):
     lib.oracle_free.argtypes = [ctypes.c_void_p]
     lib.oracle_threads.restype = ctypes.c_int
     lib.oracle_threads.argtypes = [ctypes.c_int]
+    lib.oracle_exit_step.restype = ctypes.c_int
+    lib.oracle_exit_step.argtypes = [_u8p, ctypes.c_int, _u8p, ctypes.c_int, ctypes.c_int]
+    lib.oracle_exit_steps.restype = None
+    lib.oracle_exit_steps.argtypes = [_u8p, _u8p, _u8p, _u8p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int,
+                                      ctypes.c_void_p]
     lib.k1_build.restype = ctypes.c_int
     lib.k1_build.argtypes = [_u8p, _u8p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p),
                              ctypes.POINTER(ctypes.c_uint64), ctypes.c_void_p]
@@ -151,6 +156,20 @@ class Oracle:
         if rc != 0:
             raise MemoryError("oracle_query failed")
         return _take_pairs(self.lib, ptr.value, ne.value, self.lib.oracle_free), cnt[:qs.n]
+
+    def exit_step(self, a, b, k: int) -> int:
+        """Steps of the exact final-diagonal early exit (rows = longer string)."""
+        a, b = _as_bytes(a), _as_bytes(b)
+        return self.lib.oracle_exit_step(a, len(a), b, len(b), k)
+
+    def exit_steps(self, seqs, pi, pj, k: int) -> np.ndarray:
+        pi = np.ascontiguousarray(pi, dtype=np.uint32)
+        pj = np.ascontiguousarray(pj, dtype=np.uint32)
+        out = np.zeros(max(1, len(pi)), dtype=np.int32)
+        chars = np.ascontiguousarray(seqs.chars) if seqs.chars.size else np.zeros(1, np.uint8)
+        self.lib.oracle_exit_steps(chars.ctypes.data, seqs.offsets.ctypes.data, pi.ctypes.data, pj.ctypes.data,
+                                   len(pi), k, self.nthreads, out.ctypes.data)
+        return out[:len(pi)]
 
     def k1_build(self, seqs):
         """Closed-form threshold-1 network (no DP): edges, degree."""

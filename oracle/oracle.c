@@ -35,14 +35,10 @@
 #endif
 
 /* ---------------------------------------------------------------- distance */
-int oracle_lev(const uint8_t* a, int m, const uint8_t* b, int n) {
-  int stack_tab[33 * 33];
-  int* D = stack_tab;
+/* Fill the full (m+1) x (n+1) table D (row-major, width n+1) for rows a and
+   columns b.  D must hold (m+1)*(n+1) ints. */
+static void dp_fill(const uint8_t* a, int m, const uint8_t* b, int n, int* D) {
   int w = n + 1;
-  if ((m + 1) * (n + 1) > 33 * 33) {
-    D = (int*)malloc(sizeof(int) * (size_t)(m + 1) * (size_t)(n + 1));
-    if (!D) return -1;
-  }
   for (int i = 0; i <= m; ++i) D[i * w + 0] = i;
   for (int j = 0; j <= n; ++j) D[0 * w + j] = j;
   for (int i = 1; i <= m; ++i) {
@@ -56,7 +52,17 @@ int oracle_lev(const uint8_t* a, int m, const uint8_t* b, int n) {
       D[i * w + j] = best;
     }
   }
-  int r = D[m * w + n];
+}
+
+int oracle_lev(const uint8_t* a, int m, const uint8_t* b, int n) {
+  int stack_tab[33 * 33];
+  int* D = stack_tab;
+  if ((m + 1) * (n + 1) > 33 * 33) {
+    D = (int*)malloc(sizeof(int) * (size_t)(m + 1) * (size_t)(n + 1));
+    if (!D) return -1;
+  }
+  dp_fill(a, m, b, n, D);
+  int r = D[m * (n + 1) + n];
   if (D != stack_tab) free(D);
   return r;
 }
@@ -235,3 +241,51 @@ int oracle_query(const uint8_t* rchars, const uint64_t* roffs, uint32_t r,
 void oracle_free(void* p) { free(p); }
 
 int oracle_threads(int nthreads) { return max_threads(nthreads); }
+
+/*
+ * Algorithmic-work model of the early-exit rule (used to price the work of a
+ * network build, not to decide edges).  Rows are the longer string (m),
+ * columns the shorter (n <= m).  Returns the first column j in [1, n] whose
+ * cell on the final diagonal, D[j + m - n][j], exceeds k, or n if none does.
+ * D does not decrease along a diagonal, so that cell bounds D[m][n] from
+ * below: a pair with lev <= k always returns n.
+ */
+int oracle_exit_step(const uint8_t* a, int m, const uint8_t* b, int n, int k) {
+  if (m < n) {
+    const uint8_t* t = a;
+    a = b;
+    b = t;
+    int q = m;
+    m = n;
+    n = q;
+  }
+  int stack_tab[33 * 33];
+  int* D = stack_tab;
+  int w = n + 1;
+  if ((m + 1) * (n + 1) > 33 * 33) {
+    D = (int*)malloc(sizeof(int) * (size_t)(m + 1) * (size_t)(n + 1));
+    if (!D) return -1;
+  }
+  dp_fill(a, m, b, n, D);
+  int s = n;
+  for (int j = 1; j <= n; ++j) {
+    if (D[(j + m - n) * w + j] > k) {
+      s = j;
+      break;
+    }
+  }
+  if (D != stack_tab) free(D);
+  return s;
+}
+
+/* oracle_exit_step over `count` pairs (pi[q], pj[q]) of one sequence set. */
+void oracle_exit_steps(const uint8_t* chars, const uint64_t* offsets, const uint32_t* pi, const uint32_t* pj,
+                       uint64_t count, int32_t k, int nthreads, int32_t* out) {
+  int nt = max_threads(nthreads);
+#pragma omp parallel for schedule(static) num_threads(nt)
+  for (int64_t q = 0; q < (int64_t)count; ++q) {
+    const uint32_t i = pi[q], j = pj[q];
+    out[q] = oracle_exit_step(chars + offsets[i], (int)(offsets[i + 1] - offsets[i]), chars + offsets[j],
+                              (int)(offsets[j + 1] - offsets[j]), k);
+  }
+}

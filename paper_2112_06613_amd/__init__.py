@@ -1,0 +1,274 @@
+"""Python binding of libtcrnet (thresholded all-pairs Levenshtein networks on
+MI355X).  Argument marshalling only: every step of the computation runs in the
+library's HIP kernels.  The functions carry the C names of include/tcrnet.h.
+
+The library must be built (``python -m paper_2112_06613_amd.build_lib``);
+loading fails loudly if it is missing -- there is no CPU fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from dataclasses import dataclass, field
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libtcrnet.so")
+
+TCRNET_OK, TCRNET_EINVAL, TCRNET_ENOMEM, TCRNET_EDEVICE, TCRNET_ESTATE, TCRNET_ETRUNC = range(6)
+TCRNET_F_NO_AUTOTUNE = 1
+TCRNET_F_PEQ_LDS = 2
+MAX_LEN = 32
+MAX_K = 31
+
+
+class TcrnetError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{_status_name(status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+def _status_name(s: int) -> str:
+    names = ["TCRNET_OK", "TCRNET_EINVAL", "TCRNET_ENOMEM", "TCRNET_EDEVICE", "TCRNET_ESTATE", "TCRNET_ETRUNC"]
+    return names[s] if 0 <= s < len(names) else f"status {s}"
+
+
+# ------------------------------------------------------------------ C types
+class tcrnet_seqs(ctypes.Structure):
+    _fields_ = [("data", ctypes.c_void_p), ("offsets", ctypes.c_void_p), ("n", ctypes.c_uint32)]
+
+
+class tcrnet_opts(ctypes.Structure):
+    _fields_ = [("texts_per_item", ctypes.c_uint32), ("waves_per_simd", ctypes.c_uint32),
+                ("edge_capacity", ctypes.c_uint64), ("hbm_budget", ctypes.c_uint64),
+                ("max_inflight", ctypes.c_uint32), ("flags", ctypes.c_uint32)]
+
+
+class tcrnet_build_info(ctypes.Structure):
+    _fields_ = [("evaluated_pairs", ctypes.c_uint64), ("pair_kernel_ms", ctypes.c_double),
+                ("build_ms", ctypes.c_double), ("pair_launches", ctypes.c_uint32),
+                ("texts_per_item", ctypes.c_uint32), ("waves_per_simd", ctypes.c_uint32),
+                ("peq_lds", ctypes.c_uint32)]
+
+
+class tcrnet_result_info(ctypes.Structure):
+    _fields_ = [("seqno", ctypes.c_uint64), ("snapshot_size", ctypes.c_uint32), ("is_insert", ctypes.c_uint32),
+                ("latency_ms", ctypes.c_double), ("device_ms", ctypes.c_double)]
+
+
+_P = ctypes.c_void_p
+_PP = ctypes.POINTER(ctypes.c_void_p)
+_U64P = ctypes.POINTER(ctypes.c_uint64)
+_U32P = ctypes.POINTER(ctypes.c_uint32)
+_I32 = ctypes.c_int32
+
+# (name, restype, argtypes)
+_SIGS = [
+    ("tcrnet_ctx_create", _I32, [_I32, ctypes.POINTER(tcrnet_opts), _PP]),
+    ("tcrnet_ctx_destroy", _I32, [_P]),
+    ("tcrnet_last_error", ctypes.c_char_p, []),
+    ("tcrnet_status_string", ctypes.c_char_p, [_I32]),
+    ("tcrnet_version", ctypes.c_char_p, []),
+    ("tcrnet_build", _I32, [_P, ctypes.POINTER(tcrnet_seqs), _I32, _PP]),
+    ("tcrnet_build_device", _I32, [_P, _P, _P, ctypes.c_uint32, _I32, _P, _P, ctypes.c_uint64, _P, _U64P]),
+    ("tcrnet_build_batch", _I32, [_P, ctypes.POINTER(tcrnet_seqs), ctypes.c_uint32, _I32, _PP]),
+    ("tcrnet_graph_edges", _I32, [_P, _PP, _U64P]),
+    ("tcrnet_graph_degree", _I32, [_P, _PP, _U32P]),
+    ("tcrnet_graph_info", _I32, [_P, ctypes.POINTER(tcrnet_build_info)]),
+    ("tcrnet_ctx_last_info", _I32, [_P, ctypes.POINTER(tcrnet_build_info)]),
+    ("tcrnet_graph_free", None, [_P]),
+    ("tcrnet_autotune", _I32, [_P, ctypes.POINTER(tcrnet_seqs), _I32]),
+    ("tcrnet_index_create", _I32, [_P, ctypes.POINTER(tcrnet_seqs), _I32, _PP]),
+    ("tcrnet_index_size", _I32, [_P, _U32P]),
+    ("tcrnet_index_degree", _I32, [_P, _PP, _U32P]),
+    ("tcrnet_index_free", None, [_P]),
+    ("tcrnet_query", _I32, [_P, ctypes.POINTER(tcrnet_seqs), _I32, _PP]),
+    ("tcrnet_insert", _I32, [_P, ctypes.POINTER(tcrnet_seqs), _PP]),
+    ("tcrnet_submit", _I32, [_P, ctypes.POINTER(tcrnet_seqs), _I32, _I32, _U64P]),
+    ("tcrnet_wait", _I32, [_P, ctypes.c_uint64, _PP]),
+    ("tcrnet_result_pairs", _I32, [_P, _PP, _U64P]),
+    ("tcrnet_result_counts", _I32, [_P, _PP, _U32P]),
+    ("tcrnet_result_info_get", _I32, [_P, ctypes.POINTER(tcrnet_result_info)]),
+    ("tcrnet_result_free", None, [_P]),
+]
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libtcrnet.so.  Raises if it is not built (no fallback)."""
+    global _lib
+    if _lib is not None and path == LIB_PATH:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is not built; run `python -m paper_2112_06613_amd.build_lib` "
+                           "(there is no CPU fallback)")
+    # PyTorch-ROCm ships its own HIP runtime with the same soname as the system
+    # one; loading torch first makes the library bind to that single runtime,
+    # so torch's device pointers and streams are valid in our calls.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
+    lib = ctypes.CDLL(path)
+    for name, res, args in _SIGS:
+        fn = getattr(lib, name, None)
+        if fn is None:
+            continue
+        fn.restype = res
+        fn.argtypes = args
+    if path == LIB_PATH:
+        _lib = lib
+    return lib
+
+
+def declared_symbols(header: str | None = None) -> list[str]:
+    """Names of the functions declared in include/*.h."""
+    import re
+    import glob
+    headers = [header] if header else sorted(glob.glob(os.path.join(os.path.dirname(_HERE), "include", "*.h")))
+    txt = "".join(open(h).read() for h in headers)
+    return sorted(set(re.findall(r"TCRNET_API\s+[\w\s\*]+?\b(tcrnet_\w+)\s*\(", txt)))
+
+
+def _check(rc: int):
+    if rc != TCRNET_OK:
+        msg = _lib.tcrnet_last_error().decode(errors="replace")
+        raise TcrnetError(rc, msg)
+
+
+# -------------------------------------------------------------- sequences
+def _as_seqs(seqs):
+    """(chars uint8, offsets uint64) from a list of str/bytes or an object with
+    .chars/.offsets arrays."""
+    if hasattr(seqs, "chars") and hasattr(seqs, "offsets"):
+        chars = np.ascontiguousarray(seqs.chars, dtype=np.uint8)
+        offs = np.ascontiguousarray(seqs.offsets, dtype=np.uint64)
+    else:
+        enc = [s.encode("ascii") if isinstance(s, str) else bytes(s) for s in seqs]
+        offs = np.zeros(len(enc) + 1, dtype=np.uint64)
+        if enc:
+            offs[1:] = np.cumsum([len(e) for e in enc])
+        chars = np.frombuffer(b"".join(enc), dtype=np.uint8).copy()
+    if chars.size == 0:
+        chars = np.zeros(1, dtype=np.uint8)
+    return chars, offs
+
+
+def _c_seqs(chars, offs) -> tcrnet_seqs:
+    return tcrnet_seqs(chars.ctypes.data, offs.ctypes.data, len(offs) - 1)
+
+
+@dataclass
+class Graph:
+    pairs: np.ndarray           # (E, 2) uint32, i < j, sorted
+    degree: np.ndarray          # (N,) int32
+    info: dict = field(default_factory=dict)
+
+
+def _info_dict(inf: tcrnet_build_info) -> dict:
+    return {f: getattr(inf, f) for f, _ in tcrnet_build_info._fields_}
+
+
+def _take_graph(g) -> Graph:
+    p = ctypes.c_void_p()
+    ne = ctypes.c_uint64()
+    _check(_lib.tcrnet_graph_edges(g, ctypes.byref(p), ctypes.byref(ne)))
+    E = ne.value
+    pairs = (np.ctypeslib.as_array(ctypes.cast(p, ctypes.POINTER(ctypes.c_uint32)), shape=(2 * E,)).copy()
+             if E else np.zeros(0, dtype=np.uint32))
+    d = ctypes.c_void_p()
+    nn = ctypes.c_uint32()
+    _check(_lib.tcrnet_graph_degree(g, ctypes.byref(d), ctypes.byref(nn)))
+    deg = (np.ctypeslib.as_array(ctypes.cast(d, ctypes.POINTER(ctypes.c_int32)), shape=(nn.value,)).copy()
+           if nn.value else np.zeros(0, dtype=np.int32))
+    inf = tcrnet_build_info()
+    _check(_lib.tcrnet_graph_info(g, ctypes.byref(inf)))
+    _lib.tcrnet_graph_free(g)
+    return Graph(pairs.reshape(-1, 2), deg, _info_dict(inf))
+
+
+# ---------------------------------------------------------------- context
+class Context:
+    """A tcrnet_ctx on one device."""
+
+    def __init__(self, device: int = 0, texts_per_item: int = 0, waves_per_simd: int = 0,
+                 edge_capacity: int = 0, hbm_budget: int = 0, max_inflight: int = 0, flags: int = 0):
+        load_library()
+        self.opts = tcrnet_opts(texts_per_item, waves_per_simd, edge_capacity, hbm_budget, max_inflight, flags)
+        h = ctypes.c_void_p()
+        _check(_lib.tcrnet_ctx_create(device, ctypes.byref(self.opts), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.tcrnet_ctx_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def last_info(self) -> dict:
+        inf = tcrnet_build_info()
+        _check(_lib.tcrnet_ctx_last_info(self.handle, ctypes.byref(inf)))
+        return _info_dict(inf)
+
+
+def tcrnet_build(ctx: Context, seqs, k: int) -> Graph:
+    chars, offs = _as_seqs(seqs)
+    s = _c_seqs(chars, offs)
+    g = ctypes.c_void_p()
+    _check(_lib.tcrnet_build(ctx.handle, ctypes.byref(s), k, ctypes.byref(g)))
+    return _take_graph(g)
+
+
+def tcrnet_build_device(ctx: Context, d_chars, d_offsets, k: int, d_pairs, d_degree, stream=None) -> int:
+    """Device-resident build.  d_chars: uint8 CUDA tensor; d_offsets: int64 CUDA
+    tensor (n+1); d_pairs: int32/uint32-sized CUDA tensor of shape (cap, 2);
+    d_degree: int32 CUDA tensor (n).  Returns E; raises TcrnetError with
+    status TCRNET_ETRUNC and attribute n_edges = E when E > cap (the outputs
+    are then partial)."""
+    n = d_offsets.numel() - 1
+    cap = d_pairs.shape[0] if d_pairs is not None else 0
+    st = stream.cuda_stream if stream is not None else None
+    ne = ctypes.c_uint64()
+    rc = _lib.tcrnet_build_device(ctx.handle, d_chars.data_ptr(), d_offsets.data_ptr(), n, k, st,
+                                  d_pairs.data_ptr() if cap else None, cap, d_degree.data_ptr(), ctypes.byref(ne))
+    if rc == TCRNET_ETRUNC:
+        err = TcrnetError(rc, _lib.tcrnet_last_error().decode())
+        err.n_edges = ne.value
+        raise err
+    _check(rc)
+    return ne.value
+
+
+def tcrnet_build_batch(ctx: Context, reps, k: int) -> list[Graph]:
+    conv = [_as_seqs(r) for r in reps]
+    arr = (tcrnet_seqs * max(1, len(conv)))()
+    for i, (c, o) in enumerate(conv):
+        arr[i] = _c_seqs(c, o)
+    outs = (ctypes.c_void_p * max(1, len(conv)))()
+    _check(_lib.tcrnet_build_batch(ctx.handle, arr, len(conv), k, outs))
+    return [_take_graph(ctypes.c_void_p(outs[i])) for i in range(len(conv))]
+
+
+def tcrnet_autotune(ctx: Context, seqs, k: int) -> None:
+    chars, offs = _as_seqs(seqs)
+    s = _c_seqs(chars, offs)
+    _check(_lib.tcrnet_autotune(ctx.handle, ctypes.byref(s), k))
+
+
+def version() -> str:
+    load_library()
+    return _lib.tcrnet_version().decode()

@@ -1,0 +1,489 @@
+// C-ABI of libtcrnet: contexts, the plain / device / batched builds, graphs
+// and the autotuner.  Serving lives in serve.cpp.
+#define TCRNET_BUILDING 1
+#include "api_internal.h"
+
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <vector>
+
+using namespace tcr;
+
+namespace tcr {
+const char* last_error_text();
+void clear_error();
+}  // namespace tcr
+
+struct tcrnet_graph {
+  uint32_t n = 0;
+  std::vector<uint32_t> pairs;
+  std::vector<int32_t> deg;
+  tcrnet_build_info info{};
+};
+
+namespace {
+
+const char kVersion[] = "tcrnet 0.1.0 (gfx950)";
+
+int32_t check_k(int32_t k) {
+  if (k < 0 || k > TCRNET_MAX_K) return set_error(TCRNET_EINVAL, "k = %d outside [0, %d]", k, TCRNET_MAX_K);
+  return TCRNET_OK;
+}
+
+// Host-side argument checks that need no residue arithmetic: pointers and
+// offset monotonicity (lengths themselves are validated on the device).
+int32_t check_host_seqs(const tcrnet_seqs* s, const char* what) {
+  if (!s) return set_error(TCRNET_EINVAL, "%s: NULL sequence set", what);
+  if (s->n && (!s->offsets || !s->data)) return set_error(TCRNET_EINVAL, "%s: NULL data or offsets", what);
+  for (uint32_t i = 0; i < s->n; ++i)
+    if (s->offsets[i + 1] < s->offsets[i])
+      return set_error(TCRNET_EINVAL, "%s: offsets decrease at sequence %u", what, i);
+  return TCRNET_OK;
+}
+
+uint64_t default_capacity(const tcrnet_ctx* ctx, uint64_t n) {
+  if (ctx->opts.edge_capacity) return ctx->opts.edge_capacity;
+  uint64_t c = 4 * n;
+  return c < 65536 ? 65536 : c;
+}
+
+}  // namespace
+
+namespace tcr {
+
+Sched pick_sched(const tcrnet_ctx* ctx, uint64_t n, int k) {
+  Sched s;
+  if (!(ctx->opts.flags & TCRNET_F_NO_AUTOTUNE)) {
+    auto it = ctx->tuned.find(std::make_pair((int)bits_for(n ? n : 1), k));
+    if (it != ctx->tuned.end()) s = it->second;
+  }
+  if (ctx->opts.texts_per_item) s.texts_per_item = ctx->opts.texts_per_item;
+  if (ctx->opts.waves_per_simd) s.waves_per_simd = ctx->opts.waves_per_simd;
+  if (ctx->opts.flags & TCRNET_F_PEQ_LDS) s.peq_lds = true;
+  // whole waves of 64 texts per item keep triangle items non-empty
+  s.texts_per_item = std::max<uint32_t>(64, (s.texts_per_item + 63) / 64 * 64);
+  s.waves_per_simd = std::min<uint32_t>(8, std::max<uint32_t>(1, s.waves_per_simd));
+  return s;
+}
+
+// Run one pipeline on device-resident input into (d_pairs, d_deg) with
+// capacity `cap`, re-running with the exact capacity once if the edge buffer
+// overflowed (when grow_ok).  Returns E in *E.
+int32_t run_pipeline(tcrnet_ctx* ctx, Pipeline& pl, PipeParams pp, hipStream_t st, bool grow_ok,
+                     DevBuf* pairs_buf, uint64_t* E, tcrnet_build_info* info) {
+  Sched sched = pick_sched(ctx, pp.n, pp.k);
+  pp.sched = sched;
+  tcrnet_build_info inf{};
+  inf.texts_per_item = sched.texts_per_item;
+  inf.waves_per_simd = sched.waves_per_simd;
+  inf.peq_lds = sched.peq_lds ? 1 : 0;
+  if (pp.n == 0) {
+    *E = 0;
+    if (info) *info = inf;
+    return TCRNET_OK;
+  }
+  for (int attempt = 0; attempt < 2; ++attempt) {
+    hipError_t e = pipeline_reserve(pl, pp.n, pp.n_seg, pp.k, sched.texts_per_item, pp.capacity);
+    if (e != hipSuccess) return hip_error(e, "workspace allocation");
+    if (pairs_buf) {
+      e = pairs_buf->ensure(pp.capacity * 8);
+      if (e != hipSuccess) return hip_error(e, "edge buffer allocation");
+      pp.d_pairs = pairs_buf->as<uint32_t>();
+    }
+    (void)hipEventRecord(ctx->ev_b0, st);
+    pipeline_enqueue(pl, pp, ctx->device, st, ctx->ev_p0, ctx->ev_p1);
+    (void)hipEventRecord(ctx->ev_b1, st);
+    Meta m;
+    e = pipeline_meta(pl, &m, st);
+    if (e != hipSuccess) return hip_error(e, "build");
+    float pk = 0.f, bt = 0.f;
+    (void)hipEventElapsedTime(&pk, ctx->ev_p0, ctx->ev_p1);
+    (void)hipEventElapsedTime(&bt, ctx->ev_b0, ctx->ev_b1);
+    inf.pair_kernel_ms += pk;
+    inf.build_ms += bt;
+    inf.pair_launches += 1;
+    inf.evaluated_pairs = m.plan.evaluated_pairs;
+    if (m.cnt.err != kNoError) return set_error(TCRNET_EINVAL, "%s", input_error_message(m.cnt.err).c_str());
+    if (m.plan.pad) return set_error(TCRNET_EDEVICE, "work plan overflow (internal)");
+    *E = m.cnt.edges;
+    if (info) *info = inf;
+    if (*E <= pp.capacity) return TCRNET_OK;
+    if (!grow_ok) return set_error(TCRNET_ETRUNC, "edge list of %llu edges exceeds the capacity %llu",
+                                   (unsigned long long)*E, (unsigned long long)pp.capacity);
+    pp.capacity = *E + *E / 16 + 1024;
+  }
+  return set_error(TCRNET_EDEVICE, "edge count changed between runs (internal)");
+}
+
+}  // namespace tcr
+
+// ---------------------------------------------------------------- context
+extern "C" {
+
+int32_t tcrnet_ctx_create(int32_t device, const tcrnet_opts* opts, tcrnet_ctx** out) {
+  if (!out) return set_error(TCRNET_EINVAL, "NULL output pointer");
+  *out = nullptr;
+  int ndev = 0;
+  hipError_t e = hipGetDeviceCount(&ndev);
+  if (e != hipSuccess || ndev == 0) return set_error(TCRNET_EDEVICE, "no HIP device available");
+  if (device < 0 || device >= ndev) return set_error(TCRNET_EDEVICE, "device %d out of range", device);
+  hipDeviceProp_t prop;
+  if ((e = hipGetDeviceProperties(&prop, device)) != hipSuccess) return hip_error(e, "hipGetDeviceProperties");
+  if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+    return set_error(TCRNET_EDEVICE, "device %d is %s; this library is built for gfx950", device, prop.gcnArchName);
+  if ((e = hipSetDevice(device)) != hipSuccess) return hip_error(e, "hipSetDevice");
+  tcrnet_ctx* c = new tcrnet_ctx();
+  c->device = device;
+  if (opts) c->opts = *opts;
+  if ((e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess) {
+    delete c;
+    return hip_error(e, "hipStreamCreate");
+  }
+  (void)hipEventCreate(&c->ev_p0);
+  (void)hipEventCreate(&c->ev_p1);
+  (void)hipEventCreate(&c->ev_b0);
+  (void)hipEventCreate(&c->ev_b1);
+  *out = c;
+  return TCRNET_OK;
+}
+
+int32_t tcrnet_ctx_destroy(tcrnet_ctx* ctx) {
+  if (!ctx) return TCRNET_OK;
+  (void)hipSetDevice(ctx->device);
+  (void)hipStreamSynchronize(ctx->stream);
+  if (ctx->batch_exec) (void)hipGraphExecDestroy(ctx->batch_exec);
+  (void)hipEventDestroy(ctx->ev_p0);
+  (void)hipEventDestroy(ctx->ev_p1);
+  (void)hipEventDestroy(ctx->ev_b0);
+  (void)hipEventDestroy(ctx->ev_b1);
+  (void)hipStreamDestroy(ctx->stream);
+  delete ctx;
+  return TCRNET_OK;
+}
+
+const char* tcrnet_last_error(void) { return last_error_text(); }
+
+const char* tcrnet_status_string(int32_t s) {
+  switch (s) {
+    case TCRNET_OK: return "TCRNET_OK";
+    case TCRNET_EINVAL: return "TCRNET_EINVAL";
+    case TCRNET_ENOMEM: return "TCRNET_ENOMEM";
+    case TCRNET_EDEVICE: return "TCRNET_EDEVICE";
+    case TCRNET_ESTATE: return "TCRNET_ESTATE";
+    case TCRNET_ETRUNC: return "TCRNET_ETRUNC";
+    default: return "TCRNET_UNKNOWN";
+  }
+}
+
+const char* tcrnet_version(void) { return kVersion; }
+
+// ----------------------------------------------------------------- builds
+int32_t tcrnet_build(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k, tcrnet_graph** out) {
+  if (!out) return set_error(TCRNET_EINVAL, "NULL output pointer");
+  *out = nullptr;
+  if (!ctx) return set_error(TCRNET_EINVAL, "NULL context");
+  int32_t rc;
+  if ((rc = check_k(k)) || (rc = check_host_seqs(seqs, "tcrnet_build"))) return rc;
+  (void)hipSetDevice(ctx->device);
+  const uint32_t n = seqs->n;
+  std::unique_ptr<tcrnet_graph> g(new tcrnet_graph());
+  g->n = n;
+  g->deg.assign(n, 0);
+  if (n > 0) {
+    const uint64_t base = seqs->offsets[0];
+    const uint64_t bytes = seqs->offsets[n] - base;
+    std::vector<uint64_t> off(n + 1);
+    for (uint32_t i = 0; i <= n; ++i) off[i] = seqs->offsets[i] - base;
+    hipError_t e;
+    if ((e = ctx->in_data.ensure(bytes ? bytes : 1)) != hipSuccess) return hip_error(e, "input allocation");
+    if ((e = ctx->in_off.ensure((n + 1) * 8)) != hipSuccess) return hip_error(e, "input allocation");
+    if ((e = ctx->out_deg.ensure((uint64_t)n * 4)) != hipSuccess) return hip_error(e, "output allocation");
+    if (bytes && (e = hipMemcpyAsync(ctx->in_data.p, seqs->data + base, bytes, hipMemcpyHostToDevice,
+                                     ctx->stream)) != hipSuccess)
+      return hip_error(e, "input copy");
+    if ((e = hipMemcpyAsync(ctx->in_off.p, off.data(), (n + 1) * 8, hipMemcpyHostToDevice, ctx->stream)) !=
+        hipSuccess)
+      return hip_error(e, "input copy");
+    PipeParams pp;
+    pp.d_data = ctx->in_data.as<char>();
+    pp.d_off = ctx->in_off.as<uint64_t>();
+    pp.n = n;
+    pp.k = k;
+    pp.capacity = default_capacity(ctx, n);
+    pp.d_deg = ctx->out_deg.as<int32_t>();
+    uint64_t E = 0;
+    rc = run_pipeline(ctx, ctx->pipe, pp, ctx->stream, true, &ctx->out_pairs, &E, &g->info);
+    if (rc) return rc;
+    g->pairs.resize(2 * E);
+    if (E && (e = hipMemcpyAsync(g->pairs.data(), ctx->out_pairs.p, E * 8, hipMemcpyDeviceToHost,
+                                 ctx->stream)) != hipSuccess)
+      return hip_error(e, "result copy");
+    if ((e = hipMemcpyAsync(g->deg.data(), ctx->out_deg.p, (uint64_t)n * 4, hipMemcpyDeviceToHost,
+                            ctx->stream)) != hipSuccess)
+      return hip_error(e, "result copy");
+    if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return hip_error(e, "result copy");
+  }
+  ctx->last = g->info;
+  *out = g.release();
+  return TCRNET_OK;
+}
+
+int32_t tcrnet_build_device(tcrnet_ctx* ctx, const char* d_data, const uint64_t* d_offsets, uint32_t n, int32_t k,
+                            void* stream, uint32_t* d_pairs, uint64_t pair_capacity, int32_t* d_degree,
+                            uint64_t* n_edges) {
+  if (!ctx || !n_edges) return set_error(TCRNET_EINVAL, "NULL context or n_edges");
+  int32_t rc;
+  if ((rc = check_k(k))) return rc;
+  if (n && (!d_data || !d_offsets || !d_degree)) return set_error(TCRNET_EINVAL, "NULL device buffer");
+  if (pair_capacity && !d_pairs) return set_error(TCRNET_EINVAL, "NULL pair buffer with nonzero capacity");
+  (void)hipSetDevice(ctx->device);
+  hipStream_t st = stream ? static_cast<hipStream_t>(stream) : ctx->stream;
+  PipeParams pp;
+  pp.d_data = d_data;
+  pp.d_off = d_offsets;
+  pp.n = n;
+  pp.k = k;
+  pp.capacity = pair_capacity ? pair_capacity : 1;
+  pp.d_pairs = d_pairs;
+  pp.d_deg = d_degree;
+  DevBuf scratch_pairs;  // only used when the caller passes no pair buffer
+  uint64_t E = 0;
+  tcrnet_build_info info{};
+  rc = run_pipeline(ctx, ctx->pipe, pp, st, false, pair_capacity ? nullptr : &scratch_pairs, &E, &info);
+  ctx->last = info;
+  *n_edges = E;
+  return rc;
+}
+
+int32_t tcrnet_graph_edges(const tcrnet_graph* g, const uint32_t** pairs, uint64_t* n_edges) {
+  if (!g || !pairs || !n_edges) return set_error(TCRNET_EINVAL, "NULL argument");
+  *pairs = g->pairs.empty() ? nullptr : g->pairs.data();
+  *n_edges = g->pairs.size() / 2;
+  return TCRNET_OK;
+}
+
+int32_t tcrnet_graph_degree(const tcrnet_graph* g, const int32_t** degree, uint32_t* n) {
+  if (!g || !degree || !n) return set_error(TCRNET_EINVAL, "NULL argument");
+  *degree = g->deg.empty() ? nullptr : g->deg.data();
+  *n = g->n;
+  return TCRNET_OK;
+}
+
+int32_t tcrnet_graph_info(const tcrnet_graph* g, tcrnet_build_info* info) {
+  if (!g || !info) return set_error(TCRNET_EINVAL, "NULL argument");
+  *info = g->info;
+  return TCRNET_OK;
+}
+
+int32_t tcrnet_ctx_last_info(const tcrnet_ctx* ctx, tcrnet_build_info* info) {
+  if (!ctx || !info) return set_error(TCRNET_EINVAL, "NULL argument");
+  *info = ctx->last;
+  return TCRNET_OK;
+}
+
+void tcrnet_graph_free(tcrnet_graph* g) { delete g; }
+
+// ----------------------------------------------------------------- batch
+int32_t tcrnet_build_batch(tcrnet_ctx* ctx, const tcrnet_seqs* reps, uint32_t n_reps, int32_t k,
+                           tcrnet_graph** outs) {
+  if (!ctx || !outs || (n_reps && !reps)) return set_error(TCRNET_EINVAL, "NULL argument");
+  for (uint32_t r = 0; r < n_reps; ++r) outs[r] = nullptr;
+  int32_t rc;
+  if ((rc = check_k(k))) return rc;
+  for (uint32_t r = 0; r < n_reps; ++r)
+    if ((rc = check_host_seqs(&reps[r], "tcrnet_build_batch"))) return rc;
+  (void)hipSetDevice(ctx->device);
+  // concatenate all repertoires; segment r holds global ids [seg[r], seg[r+1])
+  std::vector<uint32_t> seg(n_reps + 1, 0);
+  uint64_t bytes = 0, total = 0;
+  for (uint32_t r = 0; r < n_reps; ++r) {
+    total += reps[r].n;
+    if (total > 0xffffffffull) return set_error(TCRNET_EINVAL, "more than 2^32-1 sequences in one batch");
+    seg[r + 1] = (uint32_t)total;
+    if (reps[r].n) bytes += reps[r].offsets[reps[r].n] - reps[r].offsets[0];
+  }
+  const uint32_t n = (uint32_t)total;
+  std::vector<uint64_t> off(n + 1);
+  std::vector<char>& hdata = ctx->batch_host;
+  hdata.resize(bytes ? bytes : 1);
+  {
+    uint64_t pos = 0;
+    uint32_t i = 0;
+    for (uint32_t r = 0; r < n_reps; ++r) {
+      const tcrnet_seqs& s = reps[r];
+      if (!s.n) continue;
+      const uint64_t b0 = s.offsets[0], nb = s.offsets[s.n] - b0;
+      memcpy(hdata.data() + pos, s.data + b0, nb);
+      for (uint32_t q = 0; q < s.n; ++q) off[i++] = pos + (s.offsets[q] - b0);
+      pos += nb;
+    }
+    off[n] = pos;
+  }
+  hipError_t e;
+  if ((e = ctx->in_data.ensure(bytes ? bytes : 1)) != hipSuccess) return hip_error(e, "input allocation");
+  if ((e = ctx->in_off.ensure((uint64_t)(n + 1) * 8)) != hipSuccess) return hip_error(e, "input allocation");
+  if ((e = ctx->in_seg.ensure((uint64_t)(n_reps + 1) * 4)) != hipSuccess) return hip_error(e, "input allocation");
+  if ((e = ctx->out_deg.ensure((uint64_t)(n ? n : 1) * 4)) != hipSuccess) return hip_error(e, "output allocation");
+  if (bytes) (void)hipMemcpyAsync(ctx->in_data.p, hdata.data(), bytes, hipMemcpyHostToDevice, ctx->stream);
+  (void)hipMemcpyAsync(ctx->in_off.p, off.data(), (uint64_t)(n + 1) * 8, hipMemcpyHostToDevice, ctx->stream);
+  (void)hipMemcpyAsync(ctx->in_seg.p, seg.data(), (uint64_t)(n_reps + 1) * 4, hipMemcpyHostToDevice, ctx->stream);
+
+  PipeParams pp;
+  pp.d_data = ctx->in_data.as<char>();
+  pp.d_off = ctx->in_off.as<uint64_t>();
+  pp.n = n;
+  pp.d_segoff = ctx->in_seg.as<uint32_t>();
+  pp.n_seg = n_reps ? n_reps : 1;
+  pp.k = k;
+  pp.capacity = default_capacity(ctx, n);
+  pp.d_deg = ctx->out_deg.as<int32_t>();
+  Sched sched = pick_sched(ctx, n, k);
+  pp.sched = sched;
+  tcrnet_build_info info{};
+  info.texts_per_item = sched.texts_per_item;
+  info.waves_per_simd = sched.waves_per_simd;
+  info.peq_lds = sched.peq_lds;
+  uint64_t E = 0;
+  if (n > 0) {
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      if ((e = pipeline_reserve(ctx->pipe, n, pp.n_seg, k, sched.texts_per_item, pp.capacity)) != hipSuccess)
+        return hip_error(e, "workspace allocation");
+      if ((e = ctx->out_pairs.ensure(pp.capacity * 8)) != hipSuccess) return hip_error(e, "output allocation");
+      pp.d_pairs = ctx->out_pairs.as<uint32_t>();
+      // one HIP graph for the whole launch sequence, re-captured only when
+      // the shape or a buffer changes
+      BatchKey key{n, pp.n_seg, k, sched.texts_per_item, sched.waves_per_simd, sched.peq_lds, pp.capacity,
+                   ctx->pipe.rec.p, ctx->pipe.edges.p, ctx->pipe.tmp.p, ctx->out_pairs.p, ctx->in_data.p};
+      if (!ctx->batch_exec || !(key == ctx->batch_key)) {
+        if (ctx->batch_exec) {
+          (void)hipGraphExecDestroy(ctx->batch_exec);
+          ctx->batch_exec = nullptr;
+        }
+        hipGraph_t graph = nullptr;
+        if ((e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+          return hip_error(e, "graph capture");
+        pipeline_enqueue(ctx->pipe, pp, ctx->device, ctx->stream, nullptr, nullptr);
+        if ((e = hipStreamEndCapture(ctx->stream, &graph)) != hipSuccess) return hip_error(e, "graph capture");
+        e = hipGraphInstantiate(&ctx->batch_exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+          ctx->batch_exec = nullptr;
+          return hip_error(e, "graph instantiate");
+        }
+        ctx->batch_key = key;
+      }
+      (void)hipEventRecord(ctx->ev_b0, ctx->stream);
+      if ((e = hipGraphLaunch(ctx->batch_exec, ctx->stream)) != hipSuccess) return hip_error(e, "graph launch");
+      (void)hipEventRecord(ctx->ev_b1, ctx->stream);
+      Meta m;
+      if ((e = pipeline_meta(ctx->pipe, &m, ctx->stream)) != hipSuccess) return hip_error(e, "batch build");
+      float bt = 0.f;
+      (void)hipEventElapsedTime(&bt, ctx->ev_b0, ctx->ev_b1);
+      info.build_ms += bt;
+      info.pair_launches += 1;
+      info.evaluated_pairs = m.plan.evaluated_pairs;
+      if (m.cnt.err != kNoError) {
+        const unsigned long long idx = m.cnt.err >> 2;
+        const uint32_t r = (uint32_t)(std::upper_bound(seg.begin(), seg.end(), (uint32_t)idx) - seg.begin()) - 1;
+        return set_error(TCRNET_EINVAL, "repertoire %u, %s", r,
+                         input_error_message(((idx - seg[r]) << 2) | (m.cnt.err & 3u)).c_str());
+      }
+      if (m.plan.pad) return set_error(TCRNET_EDEVICE, "work plan overflow (internal)");
+      E = m.cnt.edges;
+      if (E <= pp.capacity) break;
+      pp.capacity = E + E / 16 + 1024;
+      if (attempt == 1) return set_error(TCRNET_EDEVICE, "edge count changed between runs (internal)");
+    }
+  }
+  // split by repertoire: edges are sorted by global (i, j), so each
+  // repertoire's edges are one contiguous run
+  std::vector<uint32_t> all(2 * E);
+  std::vector<int32_t> deg(n);
+  if (E) (void)hipMemcpyAsync(all.data(), ctx->out_pairs.p, E * 8, hipMemcpyDeviceToHost, ctx->stream);
+  if (n) (void)hipMemcpyAsync(deg.data(), ctx->out_deg.p, (uint64_t)n * 4, hipMemcpyDeviceToHost, ctx->stream);
+  if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return hip_error(e, "result copy");
+  std::vector<tcrnet_graph*> made(n_reps, nullptr);
+  uint64_t pos = 0;
+  for (uint32_t r = 0; r < n_reps; ++r) {
+    tcrnet_graph* g = new tcrnet_graph();
+    const uint32_t b = seg[r], en = seg[r + 1];
+    g->n = en - b;
+    g->deg.assign(deg.begin() + b, deg.begin() + en);
+    uint64_t q = pos;
+    while (q < E && all[2 * q] < en) ++q;
+    g->pairs.resize(2 * (q - pos));
+    for (uint64_t x = pos; x < q; ++x) {
+      g->pairs[2 * (x - pos)] = all[2 * x] - b;
+      g->pairs[2 * (x - pos) + 1] = all[2 * x + 1] - b;
+    }
+    pos = q;
+    g->info = info;
+    made[r] = g;
+  }
+  for (uint32_t r = 0; r < n_reps; ++r) outs[r] = made[r];
+  ctx->last = info;
+  return TCRNET_OK;
+}
+
+// --------------------------------------------------------------- autotune
+int32_t tcrnet_autotune(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k) {
+  if (!ctx) return set_error(TCRNET_EINVAL, "NULL context");
+  int32_t rc;
+  if ((rc = check_k(k)) || (rc = check_host_seqs(seqs, "tcrnet_autotune"))) return rc;
+  if (seqs->n < 2) return TCRNET_OK;
+  (void)hipSetDevice(ctx->device);
+  const uint32_t n = seqs->n;
+  const uint64_t base = seqs->offsets[0];
+  const uint64_t bytes = seqs->offsets[n] - base;
+  std::vector<uint64_t> off(n + 1);
+  for (uint32_t i = 0; i <= n; ++i) off[i] = seqs->offsets[i] - base;
+  hipError_t e;
+  if ((e = ctx->in_data.ensure(bytes ? bytes : 1)) != hipSuccess) return hip_error(e, "input allocation");
+  if ((e = ctx->in_off.ensure((n + 1) * 8)) != hipSuccess) return hip_error(e, "input allocation");
+  if ((e = ctx->out_deg.ensure((uint64_t)n * 4)) != hipSuccess) return hip_error(e, "output allocation");
+  (void)hipMemcpyAsync(ctx->in_data.p, seqs->data + base, bytes, hipMemcpyHostToDevice, ctx->stream);
+  (void)hipMemcpyAsync(ctx->in_off.p, off.data(), (n + 1) * 8, hipMemcpyHostToDevice, ctx->stream);
+  const uint32_t saved_flags = ctx->opts.flags;
+  const tcrnet_opts saved = ctx->opts;
+  const uint32_t Ts[] = {256, 512, 1024, 2048};
+  const uint32_t Ws[] = {4, 6, 8};
+  const bool Ls[] = {false, true};
+  double best = 1e30;
+  Sched best_s;
+  for (uint32_t T : Ts)
+    for (uint32_t W : Ws)
+      for (bool L : Ls) {
+        ctx->opts = saved;
+        ctx->opts.flags = (saved_flags | TCRNET_F_NO_AUTOTUNE) & ~TCRNET_F_PEQ_LDS;
+        if (L) ctx->opts.flags |= TCRNET_F_PEQ_LDS;
+        ctx->opts.texts_per_item = T;
+        ctx->opts.waves_per_simd = W;
+        PipeParams pp;
+        pp.d_data = ctx->in_data.as<char>();
+        pp.d_off = ctx->in_off.as<uint64_t>();
+        pp.n = n;
+        pp.k = k;
+        pp.capacity = default_capacity(ctx, n);
+        pp.d_deg = ctx->out_deg.as<int32_t>();
+        uint64_t E = 0;
+        tcrnet_build_info info{};
+        rc = run_pipeline(ctx, ctx->pipe, pp, ctx->stream, true, &ctx->out_pairs, &E, &info);
+        if (rc) {
+          ctx->opts = saved;
+          return rc;
+        }
+        const double t = info.pair_kernel_ms / (info.pair_launches ? info.pair_launches : 1);
+        if (t < best) {
+          best = t;
+          best_s.texts_per_item = T;
+          best_s.waves_per_simd = W;
+          best_s.peq_lds = L;
+        }
+      }
+  ctx->opts = saved;
+  ctx->tuned[std::make_pair((int)bits_for(n), (int)k)] = best_s;
+  return TCRNET_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,65 @@
+// Internal definitions shared by the library's host and device code.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace tcr {
+
+constexpr int kMaxLen = 32;      // one 32-bit bit-vector word per pattern
+constexpr int kAlpha = 20;       // amino-acid alphabet size
+constexpr int kWave = 64;        // CDNA wavefront
+constexpr int kBlock = 256;      // threads per block of the pair kernel (4 waves)
+constexpr uint32_t kQueryTag = 0x80000000u;  // id bit marking the query side
+
+// One sequence as the pair kernel reads it (32 bytes, read with one scalar
+// load when the sequence is the wave-uniform text).
+//   w[0..5]: 5-bit residue codes, 6 per word, code q in w[q/6] bits 5*(q%6)
+//   len:     number of residues (1..32)
+//   id:      caller-visible node id (input position; in query mode the query
+//            side carries kQueryTag)
+struct alignas(32) SeqRec {
+  uint32_t w[6];
+  uint32_t len;
+  uint32_t id;
+};
+
+// Bit masks of one pattern: eq[c] has bit q set iff residue q has code c
+// (Myers' Peq table).  80 bytes.
+struct PeqRec {
+  uint32_t eq[kAlpha];
+};
+
+// One pair of length buckets (pattern bucket of length m, text bucket of
+// length n): a rectangle of work items, or an upper triangle when both are the
+// same bucket of the same segment.  Items are (pattern group of 64, chunk of
+// texts_per_item texts), numbered group-major.
+struct alignas(16) Desc {
+  uint32_t p0, np;       // pattern range (sorted positions)
+  uint32_t t0, nt;       // text range
+  uint32_t m, n;         // lengths
+  uint32_t tri;          // 1: pairs (p, t) with p < t only
+  uint32_t chunks;       // ceil(nt / texts_per_item)
+  uint64_t item_base;    // first item of this descriptor
+  uint64_t items;        // groups * chunks
+};
+
+// Per-launch plan header written by the planning kernel.
+struct Plan {
+  uint64_t total_items;
+  uint64_t evaluated_pairs;
+  uint32_t n_desc;
+  uint32_t pad;
+};
+
+// Work counters of one build (zeroed before the encode kernel).
+struct Counters {
+  unsigned long long item_next;   // next work item to hand out
+  unsigned long long edges;       // edges found (may exceed the capacity)
+  unsigned long long err;         // min over bad inputs of (index << 2 | code),
+                                  // code 1: residue outside the alphabet,
+                                  // code 2: length 0 or > 32; ~0: none
+  unsigned long long pad;
+};
+constexpr unsigned long long kNoError = ~0ull;
+
+}  // namespace tcr

@@ -1,0 +1,83 @@
+// Launchers of the library's HIP kernels (all asynchronous on `st`).
+#pragma once
+#include "common.h"
+
+namespace tcr {
+
+// Fill n 32-bit words with v (used instead of hipMemsetAsync so that the
+// sequence can be captured in a HIP graph).
+void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
+
+// Zero the work counters and mark "no input error".
+void launch_reset_counters(Counters* c, hipStream_t st);
+
+// Step a1: validate + encode.  Sequence i of the concatenated input is
+// d_data[d_off[i] .. d_off[i+1]).  Segment of i: seg_off[s] <= i < seg_off[s+1]
+// (n_seg segments; the plain build has one).  Writes rec[i] (original order),
+// a sort key (segment, length, first residues) and value i; records the first
+// invalid sequence in cnt->err_first / err_code.  rec[i].id = (id_base + i) | id_tag.
+// seg_off may be NULL when n_seg == 1.  The key is
+//   segment << (6 + 5 * nres) | length << (5 * nres) | first nres residues,
+// with nres = (58 - seg_bits) / 5, so key_bits = seg_bits + 6 + 5 * nres.
+int encode_key_bits(uint32_t seg_bits);
+int encode_combo_shift(uint32_t seg_bits);
+void launch_encode(const char* d_data, const uint64_t* d_off, uint32_t n, const uint32_t* seg_off,
+                   uint32_t n_seg, uint32_t seg_bits, uint32_t id_base, uint32_t id_tag, SeqRec* rec,
+                   uint64_t* key, uint32_t* val, Counters* cnt, hipStream_t st);
+
+// Stable LSD radix sort of (key, val) pairs by key bits [0, key_bits), 8 bits a
+// pass.  Buffers are ping-ponged; returns true if the result ended in the
+// *_alt buffers.  val may be NULL (keys only).  tmp must hold
+// radix_tmp_words(n) words.  The element count is min(n, *d_n) when d_n is
+// not NULL (read on the device, so the launch sequence needs no host sync);
+// grids are sized for n.
+uint64_t radix_tmp_words(uint64_t n);
+bool radix_sort(uint64_t* key, uint64_t* key_alt, uint32_t* val, uint32_t* val_alt, uint64_t n,
+                const unsigned long long* d_n, int key_bits, uint32_t* tmp, hipStream_t st);
+
+// Step a2: bucket boundaries.  key holds sorted keys; combo = key >> combo_shift
+// is (segment * 33 + length).  off[c] = first sorted position whose combo >= c,
+// for c in [0, n_combo]; off[n_combo] = n.
+void launch_bucket_bounds(const uint64_t* key, uint64_t n, int combo_shift, uint32_t n_combo,
+                          uint32_t* off, hipStream_t st);
+
+// Gather records into sorted order and build each pattern's bit masks.
+void launch_gather(const SeqRec* rec, const uint32_t* val, uint64_t n, SeqRec* srec, PeqRec* speq,
+                   hipStream_t st);
+
+// Step a3: bucket-pair work plan.  One entry per (segment, m, delta) with
+// n = m - delta, 0 <= delta <= k.  Writes descs (compacted, in item order),
+// their item_base array, and the plan header.  max_desc bounds the output.
+uint32_t plan_max_desc(uint32_t n_seg, const uint32_t* host_counts_or_null, int k, uint32_t texts_per_item,
+                       uint64_t n);
+void launch_plan(const uint32_t* off, uint32_t n_seg, int k, uint32_t texts_per_item, Desc* descs,
+                 uint64_t* item_base, uint32_t max_desc, Plan* plan, hipStream_t st);
+
+// Steps a5-a6: the pair kernel (persistent grid).
+struct PairArgs {
+  const Desc* descs;
+  const uint64_t* item_base;
+  const Plan* plan;
+  const SeqRec* prec;   // pattern-side records (lane side)
+  const PeqRec* ppeq;   // pattern-side bit masks
+  const SeqRec* trec;   // text-side records (wave-uniform side)
+  Counters* cnt;
+  uint32_t* edges;      // 2 * capacity words
+  uint64_t capacity;
+  uint32_t texts_per_item;
+  int32_t k;
+};
+void launch_pairs(const PairArgs& a, uint32_t grid_blocks, bool peq_lds, hipStream_t st);
+uint32_t pair_grid_blocks(int device, uint32_t waves_per_simd);
+
+// Step a8: canonical keys.  mode 0: (min, max) of the ids.  mode 1: the id
+// carrying kQueryTag first (tag removed).  key = (first << shift) | second.
+// The edge count is min(E_max, *dE) (dE may be NULL).
+void launch_edge_keys(const uint32_t* edges, uint64_t E_max, const unsigned long long* dE, int mode, int shift,
+                      uint64_t* keys, hipStream_t st);
+// Step a7: unpack sorted keys to pairs and add both ends (mode 0) or the
+// first end (mode 1) to deg (NULL: no degrees).
+void launch_unpack(const uint64_t* keys, uint64_t E_max, const unsigned long long* dE, int mode, int shift,
+                   uint32_t* pairs, int32_t* deg, hipStream_t st);
+
+}  // namespace tcr

@@ -1,0 +1,194 @@
+// Steps a4-a6: the bucket-pair kernel.
+//
+// Distance: the bit-parallel global edit distance of Myers (J. ACM 46(3),
+// 1999) in the formulation of Hyyro (2001/2003), one 32-bit word per pattern.
+// Column j of the DP table (text prefix of length j) is held as vertical
+// deltas VP (+1) and VN (-1); the top row is D[0][j] = j, so the horizontal
+// delta entering row 1 is +1 at every step (the "| 1" after the shift).
+//
+// Early exit: D never decreases along a diagonal (Ukkonen 1985), so after
+// text step j the cell D[r][j] on the final diagonal r = j + m - n is a lower
+// bound of lev = D[m][n].  It is read from the deltas:
+//   D[r][j] = j + popcount(VP & (2^r - 1)) - popcount(VN & (2^r - 1)).
+// The paper aborts once the smallest entry of a DP row exceeds l_max
+// ("GPU-based network generation"); the diagonal cell is the tighter exact
+// bound of the same kind.  A bound above k for every lane of a wave ends the
+// wave's work on that text; no lane's answer depends on when the check runs.
+//
+// Layout of the work: a wave holds 64 consecutive patterns of one length
+// bucket (one per lane, their Peq tables in VGPRs, or in LDS) and walks the
+// texts of a chunk of another (or the same) bucket; each text is
+// wave-uniform and is read with one scalar load into SGPRs.  Sequences are
+// sorted by (length, residues), so the 64 patterns of a wave share prefixes
+// and leave a text at nearly the same step.  Pattern = the longer string of
+// the pair when lengths differ (it exits earliest).
+//
+// Output: lanes whose final distance is <= k are compacted with one ballot,
+// one atomic add per wave, and consecutive edge slots (coalesced writes).
+#include "kernels.h"
+
+namespace tcr {
+
+namespace {
+
+__device__ __forceinline__ uint32_t rfl(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ uint64_t rfl64(uint64_t v) {
+  return ((uint64_t)rfl((uint32_t)(v >> 32)) << 32) | rfl((uint32_t)v);
+}
+
+__device__ __forceinline__ uint32_t low_mask(uint32_t r) { return r >= 32 ? ~0u : ((1u << r) - 1u); }
+
+template <bool kPeqLds>
+__global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs,
+                                                  const uint64_t* __restrict__ item_base,
+                                                  const Plan* __restrict__ plan,
+                                                  const SeqRec* __restrict__ prec,
+                                                  const PeqRec* __restrict__ ppeq,
+                                                  const SeqRec* __restrict__ trec, Counters* __restrict__ cnt,
+                                                  uint32_t* __restrict__ edges, uint64_t capacity,
+                                                  uint32_t T, int k) {
+  __shared__ uint32_t lds_eq[kPeqLds ? (kBlock / kWave) * kAlpha * kWave : 1];
+  const uint32_t lane = threadIdx.x & 63u;
+  const uint32_t wid = threadIdx.x >> 6;
+  const uint64_t total = plan->total_items;
+  const uint32_t nd = plan->n_desc;
+  const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  uint32_t* wave_eq = lds_eq + (kPeqLds ? wid * kAlpha * kWave : 0);
+
+  for (;;) {
+    uint64_t item = 0;
+    if (lane == 0) item = atomicAdd(&cnt->item_next, 1ull);
+    item = rfl64(item);
+    if (item >= total) break;
+
+    // descriptor holding this item: largest di with item_base[di] <= item
+    uint32_t lo = 0, hi = nd;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (item_base[mid] <= item) lo = mid; else hi = mid;
+    }
+    const Desc d = descs[lo];
+    const uint32_t local = (uint32_t)(item - d.item_base);
+    const uint32_t g = local / d.chunks;
+    const uint32_t c = local - g * d.chunks;
+    const uint32_t gbase = d.p0 + g * kWave;
+    const bool lane_ok = g * kWave + lane < d.np;
+    const uint32_t p = lane_ok ? gbase + lane : d.p0;
+    const uint64_t lane_mask = __ballot(lane_ok);
+
+    uint32_t eq[kAlpha];
+    {
+      const PeqRec pr = ppeq[p];
+#pragma unroll
+      for (int a = 0; a < kAlpha; ++a) eq[a] = pr.eq[a];
+    }
+    if (kPeqLds) {
+#pragma unroll
+      for (int a = 0; a < kAlpha; ++a) wave_eq[a * kWave + lane] = eq[a];
+      __builtin_amdgcn_wave_barrier();
+    }
+    const uint32_t pid = prec[p].id;
+
+    const uint32_t m = d.m, n = d.n;
+    const uint32_t Mm = low_mask(m);
+    uint32_t tb = d.t0 + c * T;
+    const uint32_t te = min(d.t0 + d.nt, tb + T);
+    if (d.tri && tb < gbase + 1) tb = gbase + 1;
+
+    for (uint32_t t = tb; t < te; ++t) {
+      const SeqRec tr = trec[t];
+      uint64_t valid = lane_mask;
+      if (d.tri) {
+        const uint32_t lim = t - gbase;  // lanes with pattern < text
+        if (lim < 64) valid &= (1ull << lim) - 1ull;
+      }
+
+#define TCR_EQ(cc) (kPeqLds ? wave_eq[(cc) * kWave + lane] : eq[(cc)])
+#define TCR_CODE(q) ((tr.w[(q) / 6] >> (5 * ((q) % 6))) & 31u)
+// One text step for character J (0-based, J >= 1), then the exit test on the
+// final diagonal once it has entered the table (r >= 1).
+#define TCR_STEP(J)                                                          \
+  {                                                                          \
+    if ((uint32_t)(J) >= n) goto final_check;                                \
+    const uint32_t Eq = TCR_EQ(TCR_CODE(J));                                 \
+    const uint32_t D0 = (((Eq & VP) + VP) ^ VP) | Eq | VN;                   \
+    const uint32_t HP = VN | ~(D0 | VP);                                     \
+    const uint32_t HN = D0 & VP;                                             \
+    const uint32_t X = (HP << 1) | 1u;                                       \
+    VN = X & D0;                                                             \
+    VP = (HN << 1) | ~(X | D0);                                              \
+    const int r = (J) + 1 + (int)m - (int)n;                                 \
+    if (r >= 1) {                                                            \
+      const uint32_t Mr = low_mask((uint32_t)r);                             \
+      /* D[r][J+1] <= k  <=>  popc(VP&Mr) + J + 1 <= popc(VN&Mr) + k */     \
+      const uint32_t up = (uint32_t)__popc(VP & Mr) + (uint32_t)((J) + 1);   \
+      const uint32_t dn = (uint32_t)__popc(VN & Mr) + (uint32_t)k;           \
+      if ((__ballot(up <= dn) & valid) == 0ull) goto next_text;              \
+    }                                                                        \
+  }
+
+      // text step for character 0, from VP = 1^m, VN = 0 (then Eq & VP = Eq)
+      uint32_t VP, VN;
+      {
+        const uint32_t Eq = TCR_EQ(TCR_CODE(0));
+        const uint32_t D0 = ((Eq + Mm) ^ Mm) | Eq;
+        const uint32_t HP = ~(D0 | Mm);
+        const uint32_t HN = D0 & Mm;
+        const uint32_t X = (HP << 1) | 1u;
+        VN = X & D0;
+        VP = (HN << 1) | ~(X | D0);
+      }
+      TCR_STEP(1) TCR_STEP(2) TCR_STEP(3) TCR_STEP(4) TCR_STEP(5) TCR_STEP(6) TCR_STEP(7)
+      TCR_STEP(8) TCR_STEP(9) TCR_STEP(10) TCR_STEP(11) TCR_STEP(12) TCR_STEP(13) TCR_STEP(14)
+      TCR_STEP(15) TCR_STEP(16) TCR_STEP(17) TCR_STEP(18) TCR_STEP(19) TCR_STEP(20) TCR_STEP(21)
+      TCR_STEP(22) TCR_STEP(23) TCR_STEP(24) TCR_STEP(25) TCR_STEP(26) TCR_STEP(27) TCR_STEP(28)
+      TCR_STEP(29) TCR_STEP(30) TCR_STEP(31)
+    final_check : {
+      const int dist = (int)n + __popc(VP & Mm) - __popc(VN & Mm);
+      const bool hit = ((valid >> lane) & 1ull) && dist <= k;
+      const uint64_t hm = __ballot(hit);
+      if (hm) {
+        unsigned long long base = 0;
+        if (lane == 0) base = atomicAdd(&cnt->edges, (unsigned long long)__popcll(hm));
+        base = rfl64(base);
+        if (hit) {
+          const uint64_t slot = base + (uint64_t)__popcll(hm & lt_mask);
+          if (slot < capacity) {
+            uint2 e;
+            e.x = pid;
+            e.y = tr.id;
+            *reinterpret_cast<uint2*>(edges + 2 * slot) = e;
+          }
+        }
+      }
+    }
+    next_text:;
+#undef TCR_STEP
+#undef TCR_EQ
+#undef TCR_CODE
+    }
+    if (kPeqLds) __builtin_amdgcn_wave_barrier();
+  }
+}
+
+}  // namespace
+
+uint32_t pair_grid_blocks(int device, uint32_t waves_per_simd) {
+  int cus = 256;
+  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+  if (waves_per_simd == 0) waves_per_simd = 8;
+  // a block is 4 waves, one per SIMD of a CU
+  return (uint32_t)cus * waves_per_simd;
+}
+
+void launch_pairs(const PairArgs& a, uint32_t grid_blocks, bool peq_lds, hipStream_t st) {
+  if (peq_lds)
+    hipLaunchKernelGGL(k_pairs<true>, dim3(grid_blocks), dim3(kBlock), 0, st, a.descs, a.item_base, a.plan,
+                       a.prec, a.ppeq, a.trec, a.cnt, a.edges, a.capacity, a.texts_per_item, a.k);
+  else
+    hipLaunchKernelGGL(k_pairs<false>, dim3(grid_blocks), dim3(kBlock), 0, st, a.descs, a.item_base, a.plan,
+                       a.prec, a.ppeq, a.trec, a.cnt, a.edges, a.capacity, a.texts_per_item, a.k);
+}
+
+}  // namespace tcr

@@ -1,0 +1,92 @@
+// Host-side orchestration shared by the build, batch and serving entry points.
+#pragma once
+#include <cstdarg>
+#include <cstddef>
+#include <string>
+
+#include "kernels.h"
+
+namespace tcr {
+
+// Grow-only device buffer.
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  DevBuf() = default;
+  DevBuf(const DevBuf&) = delete;
+  DevBuf& operator=(const DevBuf&) = delete;
+  ~DevBuf() { release(); }
+  void release() {
+    if (p) (void)hipFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= cap && p) return hipSuccess;
+    release();
+    const size_t nb = bytes < 256 ? 256 : bytes + bytes / 8;
+    hipError_t e = hipMalloc(&p, nb);
+    if (e == hipSuccess) cap = nb;
+    else p = nullptr;
+    return e;
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
+
+// Pair-kernel schedule.
+struct Sched {
+  uint32_t texts_per_item = 1024;
+  uint32_t waves_per_simd = 8;
+  bool peq_lds = false;
+};
+
+// Device buffers of one build pipeline (encode -> sort -> bucket -> plan ->
+// pairs -> canonicalise).  One per context, one per serving slot.
+struct Pipeline {
+  DevBuf rec, key, key2, val, val2, srec, speq, off, descs, ibase, meta, tmp, edges, ekeys, ekeys2;
+  uint64_t n_cap = 0, e_cap = 0;
+  uint32_t desc_cap = 0;
+  Counters* cnt() const { return meta.as<Counters>(); }
+  Plan* plan() const { return reinterpret_cast<Plan*>(meta.as<char>() + 64); }
+};
+
+struct Meta {  // host copy of the counters and plan header
+  Counters cnt;
+  Plan plan;
+};
+
+// Inputs and outputs of one pipeline run.
+struct PipeParams {
+  const char* d_data = nullptr;
+  const uint64_t* d_off = nullptr;
+  uint32_t n = 0;
+  const uint32_t* d_segoff = nullptr;  // NULL: one segment
+  uint32_t n_seg = 1;
+  uint32_t id_base = 0;
+  int k = 1;
+  Sched sched;
+  uint64_t capacity = 0;               // edge capacity
+  uint32_t* d_pairs = nullptr;         // 2 * capacity words (sorted output)
+  int32_t* d_deg = nullptr;            // n words
+};
+
+uint32_t bits_for(uint64_t v);  // number of bits to hold values < v (>= 1)
+
+// Allocate every buffer the pipeline needs for these sizes.
+hipError_t pipeline_reserve(Pipeline& pl, uint64_t n, uint32_t n_seg, int k, uint32_t T, uint64_t capacity);
+
+// Enqueue the whole build on `st` with no host synchronisation.  ev0/ev1 (may
+// be NULL) bracket the pair kernel.
+void pipeline_enqueue(Pipeline& pl, const PipeParams& pp, int device, hipStream_t st, hipEvent_t ev0,
+                      hipEvent_t ev1);
+
+// Copy counters and plan header to the host (synchronises `st`).
+hipError_t pipeline_meta(const Pipeline& pl, Meta* host_meta, hipStream_t st);
+
+// Error reporting (thread-local message).
+int32_t set_error(int32_t code, const char* fmt, ...);
+int32_t hip_error(hipError_t e, const char* what);
+std::string input_error_message(unsigned long long err);
+
+}  // namespace tcr

@@ -1,0 +1,67 @@
+// Steps a7-a8: canonical edge keys and degrees.
+#include "kernels.h"
+
+namespace tcr {
+
+namespace {
+
+__device__ __forceinline__ uint64_t eff_n(uint64_t n, const unsigned long long* dn) {
+  if (!dn) return n;
+  const uint64_t v = *dn;
+  return v < n ? v : n;
+}
+
+__global__ void k_edge_keys(const uint32_t* __restrict__ edges, uint64_t E_max,
+                            const unsigned long long* __restrict__ dE, int mode, int shift,
+                            uint64_t* __restrict__ keys) {
+  const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= eff_n(E_max, dE)) return;
+  const uint2 p = reinterpret_cast<const uint2*>(edges)[e];
+  uint32_t a, b;
+  if (mode == 0) {
+    a = min(p.x, p.y);
+    b = max(p.x, p.y);
+  } else {
+    // the query-side id carries the tag; it goes first, untagged
+    const bool x_is_q = (p.x & kQueryTag) != 0;
+    a = (x_is_q ? p.x : p.y) & ~kQueryTag;
+    b = x_is_q ? p.y : p.x;
+  }
+  keys[e] = ((uint64_t)a << shift) | b;
+}
+
+__global__ void k_unpack(const uint64_t* __restrict__ keys, uint64_t E_max,
+                         const unsigned long long* __restrict__ dE, int mode, int shift,
+                         uint32_t* __restrict__ pairs, int32_t* __restrict__ deg) {
+  const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= eff_n(E_max, dE)) return;
+  const uint64_t kv = keys[e];
+  const uint32_t a = (uint32_t)(kv >> shift);
+  const uint32_t b = (uint32_t)(kv & ((1ull << shift) - 1ull));
+  uint2 p;
+  p.x = a;
+  p.y = b;
+  reinterpret_cast<uint2*>(pairs)[e] = p;
+  if (deg) {
+    atomicAdd(&deg[a], 1);
+    if (mode == 0) atomicAdd(&deg[b], 1);
+  }
+}
+
+}  // namespace
+
+void launch_edge_keys(const uint32_t* edges, uint64_t E_max, const unsigned long long* dE, int mode, int shift,
+                      uint64_t* keys, hipStream_t st) {
+  if (E_max == 0) return;
+  hipLaunchKernelGGL(k_edge_keys, dim3((uint32_t)((E_max + 255) / 256)), dim3(256), 0, st, edges, E_max, dE,
+                     mode, shift, keys);
+}
+
+void launch_unpack(const uint64_t* keys, uint64_t E_max, const unsigned long long* dE, int mode, int shift,
+                   uint32_t* pairs, int32_t* deg, hipStream_t st) {
+  if (E_max == 0) return;
+  hipLaunchKernelGGL(k_unpack, dim3((uint32_t)((E_max + 255) / 256)), dim3(256), 0, st, keys, E_max, dE, mode,
+                     shift, pairs, deg);
+}
+
+}  // namespace tcr

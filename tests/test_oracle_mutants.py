@@ -25,7 +25,7 @@ MUTANTS = {
                          "      int l = (int)(offsets[j + 1] - offsets[j]);\n      if (oracle_lev(a, m, b, l) < k) {"),
     "degree_one_end": ("      degree[(*out_pairs)[2 * e + 1]] += 1;\n", ""),
     "self_pairs": ("for (uint32_t j = (uint32_t)i + 1; j < n; ++j)", "for (uint32_t j = (uint32_t)i; j < n; ++j)"),
-    "wrong_corner": ("int r = D[m * w + n];", "int r = D[m * w + (n > 0 ? n - 1 : 0)];"),
+    "wrong_corner": ("int r = D[m * (n + 1) + n];", "int r = D[m * (n + 1) + (n > 0 ? n - 1 : 0)];"),
 }
 
 

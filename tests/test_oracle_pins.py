@@ -182,3 +182,32 @@ def test_row_matches_build(orc):
     eb, _ = orc.build(s, 2, row_lo=100, row_hi=300)
     sl = e[(e[:, 0] >= 100) & (e[:, 0] < 300)]
     assert np.array_equal(eb, sl)
+
+
+def test_exit_step_model_against_bfs(orc):
+    # The work model's exit step is the first text column j whose final-
+    # diagonal cell D[j + m - n][j] exceeds k; that cell is the edit distance
+    # of the two prefixes, so the breadth-first search fixes it too.
+    dist = bfs_distances("AR", 4)
+    strs = sorted({a for a, _ in dist if a})
+    for k in (0, 1, 2):
+        for a in strs:
+            for b in strs:
+                long_, short = (a, b) if len(a) >= len(b) else (b, a)
+                m, n = len(long_), len(short)
+                want = n
+                for j in range(1, n + 1):
+                    if dist[(long_[: j + m - n], short[:j])] > k:
+                        want = j
+                        break
+                assert orc.exit_step(a, b, k) == want, (a, b, k)
+                if dist[(a, b)] <= k:
+                    assert want == n   # a true edge never exits early
+
+
+def test_exit_step_hand_examples(orc):
+    # CAS vs CWW already differ by 2 on the main diagonal after 3 columns
+    assert orc.exit_step("CASSLF", "CWWWWF", 1) == 3
+    # one deletion apart: the bound never exceeds 1
+    assert orc.exit_step("CASSF", "CASF", 1) == 4
+    assert orc.exit_step("CASSLGQETQYF", "CASSLGQETQYF", 0) == 12
