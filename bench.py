@@ -101,6 +101,83 @@ def cpu_baseline(seqs, k, target_s: float) -> dict:
                       f"({pairs} full-DP pairs, {dt:.1f} s)"}
 
 
+def batch_leg(tn, ctx, reps, k: int = 1) -> dict:
+    """Many repertoires in one captured launch sequence vs. one plain build
+    per repertoire, back to back, on the same GPU (host inputs and outputs in
+    both cases)."""
+    tot = sum(r.n for r in reps)
+    tn.tcrnet_build_batch(ctx, reps, k)          # warm-up (captures the graph)
+    t0 = time.perf_counter()
+    gs = tn.tcrnet_build_batch(ctx, reps, k)
+    t_batch = time.perf_counter() - t0
+    for r in reps[:4]:
+        tn.tcrnet_build(ctx, r, k)
+    t0 = time.perf_counter()
+    plain_edges = 0
+    for r in reps:
+        plain_edges += len(tn.tcrnet_build(ctx, r, k).pairs)
+    t_plain = time.perf_counter() - t0
+    batch_edges = sum(len(g.pairs) for g in gs)
+    assert batch_edges == plain_edges
+    logical = sum(r.n * (r.n - 1) // 2 for r in reps)
+    return {"repertoires": len(reps), "total_sequences": tot, "k": k, "edges": batch_edges,
+            "batched_ms": t_batch * 1e3, "back_to_back_ms": t_plain * 1e3, "speedup": t_plain / t_batch,
+            "batched_pairs_per_s": logical / t_batch, "back_to_back_pairs_per_s": logical / t_plain}
+
+
+def serve_leg(tn, ctx, rep, n_requests: int, log) -> dict:
+    """Resident repertoire; Poisson arrivals of query batches of 1-4,096
+    sequences (k in {1, 2}), 20% of them inserts.  Saturation rate first
+    (all requests at once), then an open-loop run at half of it."""
+    import threading
+
+    import synth
+
+    T = 80000
+    idx = tn.tcrnet_index_create(ctx, rep, 1)
+    trace = synth.request_trace(n_requests, 1.0)
+    qs = [synth.queries(r.size, T, synth.SEED_PAPER, r.qseed) for r in trace]
+    # closed loop: everything submitted at once
+    t0 = time.perf_counter()
+    ts = [tn.tcrnet_submit(idx, q, r.k, r.insert) for q, r in zip(qs, trace)]
+    for t in ts:
+        tn.tcrnet_wait(idx, t)
+    sat = n_requests / (time.perf_counter() - t0)
+    log(f"serve: saturation {sat:.1f} requests/s")
+    # open loop at half the saturation rate, fresh index
+    idx.close()
+    idx = tn.tcrnet_index_create(ctx, rep, 1)
+    rate = 0.5 * sat
+    trace = synth.request_trace(n_requests, rate)
+    qs = [synth.queries(r.size, T, synth.SEED_PAPER, r.qseed) for r in trace]
+    tickets = [None] * n_requests
+
+    def submitter():
+        start = time.perf_counter()
+        for i, r in enumerate(trace):
+            delay = start + r.t_arrival - time.perf_counter()
+            if delay > 0:
+                time.sleep(delay)
+            tickets[i] = tn.tcrnet_submit(idx, qs[i], r.k, r.insert)
+
+    th = threading.Thread(target=submitter)
+    t0 = time.perf_counter()
+    th.start()
+    th.join()
+    res = [tn.tcrnet_wait(idx, t) for t in tickets]
+    wall = time.perf_counter() - t0
+    lat = np.array([r.info["latency_ms"] for r in res])
+    dev = np.array([r.info["device_ms"] for r in res])
+    nq = sum(r.size for r in trace)
+    final = idx.size()
+    idx.close()
+    return {"requests": n_requests, "offered_rate_hz": rate, "saturation_rate_hz": sat,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "mean_device_ms": float(dev.mean()), "requests_per_s": n_requests / wall,
+            "query_seqs_per_s": nq / wall, "inserts": int(sum(r.insert for r in trace)),
+            "resident_start": rep.n, "resident_end": final, "index_k": 1}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -111,6 +188,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (HBM counter calibration)")
     args = ap.parse_args()
@@ -188,17 +266,12 @@ def main():
         },
     }
     if not args.no_batch:
-        try:
-            from bench_forms import batch_leg
-            out["batch"] = batch_leg(tn, ctx, log)
-        except Exception as ex:  # reported, never hides the main line
-            out["batch"] = {"error": repr(ex)}
+        log("batched form (256 repertoires) ...")
+        out["batch"] = batch_leg(tn, ctx, synth.batch())
     if not args.no_serve:
-        try:
-            from bench_forms import serve_leg
-            out["serve"] = serve_leg(tn, ctx, seqs, log)
-        except Exception as ex:
-            out["serve"] = {"error": repr(ex)}
+        log("served form ...")
+        out["serve"] = serve_leg(tn, ctx, seqs, args.serve_requests, log)
+        out["serve"]["plain_rebuild_ms"] = step_s * 1e3
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(seqs, k, args.cpu_seconds)

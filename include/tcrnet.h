@@ -162,6 +162,52 @@ TCRNET_API void tcrnet_graph_free(tcrnet_graph* g);
  * are exact for every candidate; only speed differs. */
 TCRNET_API int32_t tcrnet_autotune(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k);
 
+/* ------------------------------------------------------------------ serving
+ * A resident repertoire on the device (sorted into length buckets), with its
+ * degree array at threshold k_index.  Query batches compare new sequences
+ * against the repertoire at their own k; insert batches also add their
+ * sequences (new ids N_old .. N_old+M-1) and their edges at k_index.
+ * (Paper, "Distinguishing antigens with network analysis": cognate sequences
+ * are placed into an existing network.) */
+TCRNET_API int32_t tcrnet_index_create(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k_index,
+                                       tcrnet_index** out);
+TCRNET_API int32_t tcrnet_index_size(tcrnet_index* idx, uint32_t* n);
+/* Host copy of the current degree array (valid until the next call on idx). */
+TCRNET_API int32_t tcrnet_index_degree(tcrnet_index* idx, const int32_t** degree, uint32_t* n);
+TCRNET_API void tcrnet_index_free(tcrnet_index* idx);
+
+/* Synchronous query: pairs (q, r) with lev(q_q, R_r) <= k, sorted; r are
+   repertoire ids.  counts[q] = number of such r. */
+TCRNET_API int32_t tcrnet_query(tcrnet_index* idx, const tcrnet_seqs* q, int32_t k, tcrnet_result** out);
+/* Synchronous insert: adds q to the repertoire.  Result pairs are the new
+   edges (i, j), i < j, at k_index (j is always a new id); counts[q] is the
+   degree of new node N_old + q; the degrees of old nodes are updated. */
+TCRNET_API int32_t tcrnet_insert(tcrnet_index* idx, const tcrnet_seqs* q, tcrnet_result** out);
+
+/* Asynchronous form with continuous batching.  A request is admitted when a
+   device slot and enough of the memory budget are free; requests admitted
+   while others run overlap on the device.  Each request sees the repertoire
+   as of its admission: the initial sequences plus every insert admitted
+   before it.  `insert` = 1 makes it an insert (k is then ignored and the
+   index's k is used). */
+TCRNET_API int32_t tcrnet_submit(tcrnet_index* idx, const tcrnet_seqs* q, int32_t k, int32_t insert,
+                                 uint64_t* ticket);
+/* Block until the request finishes; hands over its result (once). */
+TCRNET_API int32_t tcrnet_wait(tcrnet_index* idx, uint64_t ticket, tcrnet_result** out);
+
+typedef struct {
+  uint64_t seqno;         /* admission order */
+  uint32_t snapshot_size; /* repertoire size the request saw */
+  uint32_t is_insert;
+  double latency_ms;      /* submit -> result ready on the host */
+  double device_ms;       /* first launch -> last kernel done */
+} tcrnet_result_info;
+
+TCRNET_API int32_t tcrnet_result_pairs(const tcrnet_result* r, const uint32_t** pairs, uint64_t* n);
+TCRNET_API int32_t tcrnet_result_counts(const tcrnet_result* r, const int32_t** counts, uint32_t* n);
+TCRNET_API int32_t tcrnet_result_info_get(const tcrnet_result* r, tcrnet_result_info* info);
+TCRNET_API void tcrnet_result_free(tcrnet_result* r);
+
 #ifdef __cplusplus
 }
 #endif

@@ -272,3 +272,104 @@ def tcrnet_autotune(ctx: Context, seqs, k: int) -> None:
 def version() -> str:
     load_library()
     return _lib.tcrnet_version().decode()
+
+
+# ---------------------------------------------------------------- serving
+@dataclass
+class Result:
+    pairs: np.ndarray           # (E, 2) uint32
+    counts: np.ndarray          # (M,) int32
+    info: dict = field(default_factory=dict)
+
+
+def _take_result(r) -> Result:
+    p = ctypes.c_void_p()
+    ne = ctypes.c_uint64()
+    _check(_lib.tcrnet_result_pairs(r, ctypes.byref(p), ctypes.byref(ne)))
+    E = ne.value
+    pairs = (np.ctypeslib.as_array(ctypes.cast(p, ctypes.POINTER(ctypes.c_uint32)), shape=(2 * E,)).copy()
+             if E else np.zeros(0, dtype=np.uint32))
+    c = ctypes.c_void_p()
+    nn = ctypes.c_uint32()
+    _check(_lib.tcrnet_result_counts(r, ctypes.byref(c), ctypes.byref(nn)))
+    counts = (np.ctypeslib.as_array(ctypes.cast(c, ctypes.POINTER(ctypes.c_int32)), shape=(nn.value,)).copy()
+              if nn.value else np.zeros(0, dtype=np.int32))
+    inf = tcrnet_result_info()
+    _check(_lib.tcrnet_result_info_get(r, ctypes.byref(inf)))
+    _lib.tcrnet_result_free(r)
+    return Result(pairs.reshape(-1, 2), counts, {f: getattr(inf, f) for f, _ in tcrnet_result_info._fields_})
+
+
+class Index:
+    """A tcrnet_index: resident repertoire with query / insert service."""
+
+    def __init__(self, handle):
+        self.handle = handle
+
+    def size(self) -> int:
+        n = ctypes.c_uint32()
+        _check(_lib.tcrnet_index_size(self.handle, ctypes.byref(n)))
+        return n.value
+
+    def degree(self) -> np.ndarray:
+        d = ctypes.c_void_p()
+        n = ctypes.c_uint32()
+        _check(_lib.tcrnet_index_degree(self.handle, ctypes.byref(d), ctypes.byref(n)))
+        if not n.value:
+            return np.zeros(0, dtype=np.int32)
+        return np.ctypeslib.as_array(ctypes.cast(d, ctypes.POINTER(ctypes.c_int32)), shape=(n.value,)).copy()
+
+    def close(self):
+        if getattr(self, "handle", None):
+            _lib.tcrnet_index_free(self.handle)
+            self.handle = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+def tcrnet_index_create(ctx: Context, seqs, k_index: int) -> Index:
+    chars, offs = _as_seqs(seqs)
+    s = _c_seqs(chars, offs)
+    h = ctypes.c_void_p()
+    _check(_lib.tcrnet_index_create(ctx.handle, ctypes.byref(s), k_index, ctypes.byref(h)))
+    return Index(h)
+
+
+def tcrnet_query(idx: Index, seqs, k: int) -> Result:
+    chars, offs = _as_seqs(seqs)
+    s = _c_seqs(chars, offs)
+    r = ctypes.c_void_p()
+    _check(_lib.tcrnet_query(idx.handle, ctypes.byref(s), k, ctypes.byref(r)))
+    return _take_result(r)
+
+
+def tcrnet_insert(idx: Index, seqs) -> Result:
+    chars, offs = _as_seqs(seqs)
+    s = _c_seqs(chars, offs)
+    r = ctypes.c_void_p()
+    _check(_lib.tcrnet_insert(idx.handle, ctypes.byref(s), ctypes.byref(r)))
+    return _take_result(r)
+
+
+def tcrnet_submit(idx: Index, seqs, k: int, insert: bool = False) -> int:
+    chars, offs = _as_seqs(seqs)
+    s = _c_seqs(chars, offs)
+    t = ctypes.c_uint64()
+    _check(_lib.tcrnet_submit(idx.handle, ctypes.byref(s), k, 1 if insert else 0, ctypes.byref(t)))
+    return t.value
+
+
+def tcrnet_wait(idx: Index, ticket: int) -> Result:
+    r = ctypes.c_void_p()
+    _check(_lib.tcrnet_wait(idx.handle, ticket, ctypes.byref(r)))
+    return _take_result(r)

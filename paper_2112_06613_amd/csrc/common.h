@@ -32,15 +32,42 @@ struct PeqRec {
 // One pair of length buckets (pattern bucket of length m, text bucket of
 // length n): a rectangle of work items, or an upper triangle when both are the
 // same bucket of the same segment.  Items are (pattern group of 64, chunk of
-// texts_per_item texts), numbered group-major.
+// texts_per_item texts), numbered group-major.  The descriptor names the
+// sequence sets its patterns and texts come from, so one launch can cover
+// several sets (a query batch against a repertoire and its inserted parts).
 struct alignas(16) Desc {
-  uint32_t p0, np;       // pattern range (sorted positions)
-  uint32_t t0, nt;       // text range
+  const SeqRec* prec;    // pattern-side records (lane side)
+  const PeqRec* ppeq;    // pattern-side bit masks
+  const SeqRec* trec;    // text-side records (wave-uniform side)
+  uint32_t p0, np;       // pattern range (sorted positions in prec)
+  uint32_t t0, nt;       // text range (sorted positions in trec)
   uint32_t m, n;         // lengths
   uint32_t tri;          // 1: pairs (p, t) with p < t only
   uint32_t chunks;       // ceil(nt / texts_per_item)
   uint64_t item_base;    // first item of this descriptor
   uint64_t items;        // groups * chunks
+};
+
+// A sorted, length-bucketed sequence set: records and masks in sorted order
+// and its bucket table off[seg * 64 + L] (n_seg segments, n_seg * 64 + 1
+// entries): bucket (seg, L) = [off[seg*64+L], off[seg*64+L+1]).
+struct SetRef {
+  const SeqRec* srec;
+  const PeqRec* speq;
+  const uint32_t* off;
+  uint32_t n_seg;
+  uint32_t pad;
+};
+
+// One part of a work plan.  self (cross == 0): all pairs inside each segment
+// of set a, lengths at most k apart.  cross: all pairs between set a (one
+// segment) and set b (one segment), lengths at most k apart; when the lengths
+// are equal, a supplies the patterns.
+struct PlanPart {
+  SetRef a;
+  SetRef b;
+  uint32_t cross;
+  uint32_t pad;
 };
 
 // Per-launch plan header written by the planning kernel.

@@ -10,6 +10,12 @@ void launch_fill_u32(uint32_t* p, uint64_t n, uint32_t v, hipStream_t st);
 
 // Zero the work counters and mark "no input error".
 void launch_reset_counters(Counters* c, hipStream_t st);
+// Zero only the item and edge counters (keeps the input error).
+void launch_reset_work(Counters* c, hipStream_t st);
+
+// Sort keys (segment 0, length, first residues) and values 0..n-1 of
+// already-encoded records (layout of launch_encode with seg_bits = 0).
+void launch_record_keys(const SeqRec* rec, uint32_t n, uint64_t* key, uint32_t* val, hipStream_t st);
 
 // Step a1: validate + encode.  Sequence i of the concatenated input is
 // d_data[d_off[i] .. d_off[i+1]).  Segment of i: seg_off[s] <= i < seg_off[s+1]
@@ -45,22 +51,21 @@ void launch_bucket_bounds(const uint64_t* key, uint64_t n, int combo_shift, uint
 void launch_gather(const SeqRec* rec, const uint32_t* val, uint64_t n, SeqRec* srec, PeqRec* speq,
                    hipStream_t st);
 
-// Step a3: bucket-pair work plan.  One entry per (segment, m, delta) with
-// n = m - delta, 0 <= delta <= k.  Writes descs (compacted, in item order),
-// their item_base array, and the plan header.  max_desc bounds the output.
-uint32_t plan_max_desc(uint32_t n_seg, const uint32_t* host_counts_or_null, int k, uint32_t texts_per_item,
-                       uint64_t n);
-void launch_plan(const uint32_t* off, uint32_t n_seg, int k, uint32_t texts_per_item, Desc* descs,
-                 uint64_t* item_base, uint32_t max_desc, Plan* plan, hipStream_t st);
+// Step a3: bucket-pair work plan over a list of parts (device array d_parts
+// of n_parts entries, or the single inline_part when d_parts is NULL).
+// Writes descs (compacted, in item order), their item_base array and the
+// plan header; more than max_desc descriptors sets plan->pad = 1.
+uint32_t plan_max_desc_self(uint32_t n_seg, int k, uint32_t texts_per_item, uint64_t n);
+uint32_t plan_max_desc_cross(int k);
+void launch_plan(const PlanPart* d_parts, uint32_t n_parts, const PlanPart& inline_part, int k,
+                 uint32_t texts_per_item, Desc* descs, uint64_t* item_base, uint32_t max_desc, Plan* plan,
+                 hipStream_t st);
 
-// Steps a5-a6: the pair kernel (persistent grid).
+// Steps a4-a6: the pair kernel (persistent grid).
 struct PairArgs {
   const Desc* descs;
   const uint64_t* item_base;
   const Plan* plan;
-  const SeqRec* prec;   // pattern-side records (lane side)
-  const PeqRec* ppeq;   // pattern-side bit masks
-  const SeqRec* trec;   // text-side records (wave-uniform side)
   Counters* cnt;
   uint32_t* edges;      // 2 * capacity words
   uint64_t capacity;
@@ -75,6 +80,11 @@ uint32_t pair_grid_blocks(int device, uint32_t waves_per_simd);
 // The edge count is min(E_max, *dE) (dE may be NULL).
 void launch_edge_keys(const uint32_t* edges, uint64_t E_max, const unsigned long long* dE, int mode, int shift,
                       uint64_t* keys, hipStream_t st);
+// Degrees of an insert: for each of the E pairs (i, j) add 1 to deg[i] and
+// deg[j], and to counts[x - n_old] for each end x >= n_old.
+void launch_insert_degrees(const uint32_t* pairs, const unsigned long long* dE, uint64_t E_max, uint32_t n_old,
+                           int32_t* counts, int32_t* deg, hipStream_t st);
+
 // Step a7: unpack sorted keys to pairs and add both ends (mode 0) or the
 // first end (mode 1) to deg (NULL: no degrees).
 void launch_unpack(const uint64_t* keys, uint64_t E_max, const unsigned long long* dE, int mode, int shift,

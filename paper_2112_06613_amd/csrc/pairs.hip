@@ -39,13 +39,38 @@ __device__ __forceinline__ uint64_t rfl64(uint64_t v) {
 
 __device__ __forceinline__ uint32_t low_mask(uint32_t r) { return r >= 32 ? ~0u : ((1u << r) - 1u); }
 
+// Loads through address-space views of descriptor pointers: the wave-uniform
+// text records are read-only for the whole launch, so they are read through
+// the constant address space (scalar loads into SGPRs); pattern data through
+// the global one.  (The host compilation pass only parses kernel bodies.)
+template <class T>
+__device__ __forceinline__ T load_const(const T* p, uint32_t i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const __attribute__((address_space(4))) T* q = (const __attribute__((address_space(4))) T*)p;
+  T v;
+  __builtin_memcpy(&v, (const T*)(q + i), sizeof(T));
+  return v;
+#else
+  return p[i];
+#endif
+}
+
+template <class T>
+__device__ __forceinline__ T load_global(const T* p, uint32_t i) {
+#if defined(__HIP_DEVICE_COMPILE__)
+  const __attribute__((address_space(1))) T* q = (const __attribute__((address_space(1))) T*)p;
+  T v;
+  __builtin_memcpy(&v, (const T*)(q + i), sizeof(T));
+  return v;
+#else
+  return p[i];
+#endif
+}
+
 template <bool kPeqLds>
 __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs,
                                                   const uint64_t* __restrict__ item_base,
-                                                  const Plan* __restrict__ plan,
-                                                  const SeqRec* __restrict__ prec,
-                                                  const PeqRec* __restrict__ ppeq,
-                                                  const SeqRec* __restrict__ trec, Counters* __restrict__ cnt,
+                                                  const Plan* __restrict__ plan, Counters* __restrict__ cnt,
                                                   uint32_t* __restrict__ edges, uint64_t capacity,
                                                   uint32_t T, int k) {
   __shared__ uint32_t lds_eq[kPeqLds ? (kBlock / kWave) * kAlpha * kWave : 1];
@@ -69,6 +94,9 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
       if (item_base[mid] <= item) lo = mid; else hi = mid;
     }
     const Desc d = descs[lo];
+    const SeqRec* prec = d.prec;
+    const PeqRec* ppeq = d.ppeq;
+    const SeqRec* trec = d.trec;
     const uint32_t local = (uint32_t)(item - d.item_base);
     const uint32_t g = local / d.chunks;
     const uint32_t c = local - g * d.chunks;
@@ -79,7 +107,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
 
     uint32_t eq[kAlpha];
     {
-      const PeqRec pr = ppeq[p];
+      const PeqRec pr = load_global(ppeq, p);
 #pragma unroll
       for (int a = 0; a < kAlpha; ++a) eq[a] = pr.eq[a];
     }
@@ -88,7 +116,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
       for (int a = 0; a < kAlpha; ++a) wave_eq[a * kWave + lane] = eq[a];
       __builtin_amdgcn_wave_barrier();
     }
-    const uint32_t pid = prec[p].id;
+    const uint32_t pid = load_global(prec, p).id;
 
     const uint32_t m = d.m, n = d.n;
     const uint32_t Mm = low_mask(m);
@@ -97,7 +125,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     if (d.tri && tb < gbase + 1) tb = gbase + 1;
 
     for (uint32_t t = tb; t < te; ++t) {
-      const SeqRec tr = trec[t];
+      const SeqRec tr = load_const(trec, t);
       uint64_t valid = lane_mask;
       if (d.tri) {
         const uint32_t lim = t - gbase;  // lanes with pattern < text
@@ -185,10 +213,10 @@ uint32_t pair_grid_blocks(int device, uint32_t waves_per_simd) {
 void launch_pairs(const PairArgs& a, uint32_t grid_blocks, bool peq_lds, hipStream_t st) {
   if (peq_lds)
     hipLaunchKernelGGL(k_pairs<true>, dim3(grid_blocks), dim3(kBlock), 0, st, a.descs, a.item_base, a.plan,
-                       a.prec, a.ppeq, a.trec, a.cnt, a.edges, a.capacity, a.texts_per_item, a.k);
+                       a.cnt, a.edges, a.capacity, a.texts_per_item, a.k);
   else
     hipLaunchKernelGGL(k_pairs<false>, dim3(grid_blocks), dim3(kBlock), 0, st, a.descs, a.item_base, a.plan,
-                       a.prec, a.ppeq, a.trec, a.cnt, a.edges, a.capacity, a.texts_per_item, a.k);
+                       a.cnt, a.edges, a.capacity, a.texts_per_item, a.k);
 }
 
 }  // namespace tcr

@@ -46,9 +46,10 @@ uint32_t bits_for(uint64_t v) {
 
 static uint32_t seg_bits_for(uint32_t n_seg) { return n_seg <= 1 ? 0 : bits_for(n_seg); }
 
-hipError_t pipeline_reserve(Pipeline& pl, uint64_t n, uint32_t n_seg, int k, uint32_t T, uint64_t capacity) {
+hipError_t pipeline_reserve(Pipeline& pl, uint64_t n, uint32_t n_seg, int k, uint32_t T, uint64_t capacity,
+                            uint32_t max_desc) {
   const uint64_t nn = n ? n : 1;
-  const uint32_t max_desc = plan_max_desc(n_seg, nullptr, k, T, n);
+  if (!max_desc) max_desc = plan_max_desc_self(n_seg, k, T, n);
   const uint64_t cap = capacity ? capacity : 1;
   hipError_t e;
 #define TCR_RESERVE(buf, bytes) \
@@ -76,55 +77,95 @@ hipError_t pipeline_reserve(Pipeline& pl, uint64_t n, uint32_t n_seg, int k, uin
   return hipSuccess;
 }
 
-void pipeline_enqueue(Pipeline& pl, const PipeParams& pp, int device, hipStream_t st, hipEvent_t ev0,
-                      hipEvent_t ev1) {
-  const uint32_t n = pp.n;
-  const uint32_t seg_bits = seg_bits_for(pp.n_seg);
-  Counters* cnt = pl.cnt();
-  launch_reset_counters(cnt, st);
-  if (pp.d_deg) launch_fill_u32(reinterpret_cast<uint32_t*>(pp.d_deg), n, 0u, st);
-  if (n == 0) return;
-
-  // a1: validate + encode, a2: sort by (segment, length, residues)
-  launch_encode(pp.d_data, pp.d_off, n, pp.d_segoff, pp.n_seg, seg_bits, pp.id_base, 0u, pl.rec.as<SeqRec>(),
-                pl.key.as<uint64_t>(), pl.val.as<uint32_t>(), cnt, st);
+void stage_prepare(Pipeline& pl, const char* d_data, const uint64_t* d_off, uint32_t n, const uint32_t* d_segoff,
+                   uint32_t n_seg, uint32_t id_base, uint32_t id_tag, const SetOut& out, hipStream_t st) {
+  const uint32_t seg_bits = seg_bits_for(n_seg);
+  SeqRec* srec = out.srec ? out.srec : pl.srec.as<SeqRec>();
+  PeqRec* speq = out.speq ? out.speq : pl.speq.as<PeqRec>();
+  uint32_t* off = out.off ? out.off : pl.off.as<uint32_t>();
+  const uint32_t n_combo = n_seg * 64;
+  if (n == 0) {
+    launch_fill_u32(off, n_combo + 1, 0u, st);
+    return;
+  }
+  launch_encode(d_data, d_off, n, d_segoff, n_seg, seg_bits, id_base, id_tag, pl.rec.as<SeqRec>(),
+                pl.key.as<uint64_t>(), pl.val.as<uint32_t>(), pl.cnt(), st);
   const bool alt = radix_sort(pl.key.as<uint64_t>(), pl.key2.as<uint64_t>(), pl.val.as<uint32_t>(),
                               pl.val2.as<uint32_t>(), n, nullptr, encode_key_bits(seg_bits), pl.tmp.as<uint32_t>(),
                               st);
   const uint64_t* skey = alt ? pl.key2.as<uint64_t>() : pl.key.as<uint64_t>();
   const uint32_t* sval = alt ? pl.val2.as<uint32_t>() : pl.val.as<uint32_t>();
-  const uint32_t n_combo = pp.n_seg * 64;
-  launch_bucket_bounds(skey, n, encode_combo_shift(seg_bits), n_combo, pl.off.as<uint32_t>(), st);
-  launch_gather(pl.rec.as<SeqRec>(), sval, n, pl.srec.as<SeqRec>(), pl.speq.as<PeqRec>(), st);
+  launch_bucket_bounds(skey, n, encode_combo_shift(seg_bits), n_combo, off, st);
+  launch_gather(pl.rec.as<SeqRec>(), sval, n, srec, speq, st);
+}
 
-  // a3: bucket-pair plan
-  launch_plan(pl.off.as<uint32_t>(), pp.n_seg, pp.k, pp.sched.texts_per_item, pl.descs.as<Desc>(),
-              pl.ibase.as<uint64_t>(), pl.desc_cap, pl.plan(), st);
+void stage_prepare_records(Pipeline& pl, const SeqRec* rec, uint32_t n, const SetOut& out, hipStream_t st) {
+  SeqRec* srec = out.srec ? out.srec : pl.srec.as<SeqRec>();
+  PeqRec* speq = out.speq ? out.speq : pl.speq.as<PeqRec>();
+  uint32_t* off = out.off ? out.off : pl.off.as<uint32_t>();
+  if (n == 0) {
+    launch_fill_u32(off, 65, 0u, st);
+    return;
+  }
+  launch_record_keys(rec, n, pl.key.as<uint64_t>(), pl.val.as<uint32_t>(), st);
+  const bool alt = radix_sort(pl.key.as<uint64_t>(), pl.key2.as<uint64_t>(), pl.val.as<uint32_t>(),
+                              pl.val2.as<uint32_t>(), n, nullptr, encode_key_bits(0), pl.tmp.as<uint32_t>(), st);
+  const uint64_t* skey = alt ? pl.key2.as<uint64_t>() : pl.key.as<uint64_t>();
+  const uint32_t* sval = alt ? pl.val2.as<uint32_t>() : pl.val.as<uint32_t>();
+  launch_bucket_bounds(skey, n, encode_combo_shift(0), 64, off, st);
+  launch_gather(rec, sval, n, srec, speq, st);
+}
 
-  // a4-a6: pairs
+void stage_pairs(Pipeline& pl, const PlanPart* d_parts, uint32_t n_parts, const PlanPart& inline_part, int k,
+                 const Sched& sched, uint64_t capacity, uint32_t grid_blocks, hipStream_t st, hipEvent_t ev0,
+                 hipEvent_t ev1) {
+  Counters* cnt = pl.cnt();
+  launch_reset_work(cnt, st);
+  launch_plan(d_parts, n_parts, inline_part, k, sched.texts_per_item, pl.descs.as<Desc>(), pl.ibase.as<uint64_t>(),
+              pl.desc_cap, pl.plan(), st);
   PairArgs a;
   a.descs = pl.descs.as<Desc>();
   a.item_base = pl.ibase.as<uint64_t>();
   a.plan = pl.plan();
-  a.prec = pl.srec.as<SeqRec>();
-  a.ppeq = pl.speq.as<PeqRec>();
-  a.trec = pl.srec.as<SeqRec>();
   a.cnt = cnt;
   a.edges = pl.edges.as<uint32_t>();
-  a.capacity = pp.capacity;
-  a.texts_per_item = pp.sched.texts_per_item;
-  a.k = pp.k;
+  a.capacity = capacity;
+  a.texts_per_item = sched.texts_per_item;
+  a.k = k;
   if (ev0) (void)hipEventRecord(ev0, st);
-  launch_pairs(a, pair_grid_blocks(device, pp.sched.waves_per_simd), pp.sched.peq_lds, st);
+  launch_pairs(a, grid_blocks, sched.peq_lds, st);
   if (ev1) (void)hipEventRecord(ev1, st);
+}
 
-  // a7-a8: canonical sorted edge list and degrees
-  const int shift = (int)bits_for(n);
-  launch_edge_keys(pl.edges.as<uint32_t>(), pp.capacity, &cnt->edges, 0, shift, pl.ekeys.as<uint64_t>(), st);
-  const bool ealt = radix_sort(pl.ekeys.as<uint64_t>(), pl.ekeys2.as<uint64_t>(), nullptr, nullptr, pp.capacity,
+void stage_canon(Pipeline& pl, int mode, int shift, uint64_t capacity, uint32_t* d_pairs, int32_t* d_deg,
+                 hipStream_t st) {
+  Counters* cnt = pl.cnt();
+  launch_edge_keys(pl.edges.as<uint32_t>(), capacity, &cnt->edges, mode, shift, pl.ekeys.as<uint64_t>(), st);
+  const bool ealt = radix_sort(pl.ekeys.as<uint64_t>(), pl.ekeys2.as<uint64_t>(), nullptr, nullptr, capacity,
                                &cnt->edges, 2 * shift, pl.tmp.as<uint32_t>(), st);
   const uint64_t* sk = ealt ? pl.ekeys2.as<uint64_t>() : pl.ekeys.as<uint64_t>();
-  launch_unpack(sk, pp.capacity, &cnt->edges, 0, shift, pp.d_pairs, pp.d_deg, st);
+  launch_unpack(sk, capacity, &cnt->edges, mode, shift, d_pairs, d_deg, st);
+}
+
+void pipeline_enqueue(Pipeline& pl, const PipeParams& pp, int device, hipStream_t st, hipEvent_t ev0,
+                      hipEvent_t ev1) {
+  const uint32_t n = pp.n;
+  launch_reset_counters(pl.cnt(), st);
+  if (pp.d_deg) launch_fill_u32(reinterpret_cast<uint32_t*>(pp.d_deg), n, 0u, st);
+  if (n == 0) return;
+  // a1-a2
+  stage_prepare(pl, pp.d_data, pp.d_off, n, pp.d_segoff, pp.n_seg, pp.id_base, 0u, SetOut{}, st);
+  // a3-a6: one self part over the sorted set
+  PlanPart part{};
+  part.a.srec = pl.srec.as<SeqRec>();
+  part.a.speq = pl.speq.as<PeqRec>();
+  part.a.off = pl.off.as<uint32_t>();
+  part.a.n_seg = pp.n_seg;
+  part.cross = 0;
+  stage_pairs(pl, nullptr, 1, part, pp.k, pp.sched, pp.capacity, pair_grid_blocks(device, pp.sched.waves_per_simd),
+              st, ev0, ev1);
+  // a7-a8
+  stage_canon(pl, 0, (int)bits_for(n), pp.capacity, pp.d_pairs, pp.d_deg, st);
 }
 
 hipError_t pipeline_meta(const Pipeline& pl, Meta* host_meta, hipStream_t st) {

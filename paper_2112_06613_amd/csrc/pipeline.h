@@ -73,8 +73,35 @@ struct PipeParams {
 
 uint32_t bits_for(uint64_t v);  // number of bits to hold values < v (>= 1)
 
-// Allocate every buffer the pipeline needs for these sizes.
-hipError_t pipeline_reserve(Pipeline& pl, uint64_t n, uint32_t n_seg, int k, uint32_t T, uint64_t capacity);
+// Allocate every buffer the pipeline needs for these sizes (max_desc: 0 =
+// the bound of a self plan over n sequences in n_seg segments).
+hipError_t pipeline_reserve(Pipeline& pl, uint64_t n, uint32_t n_seg, int k, uint32_t T, uint64_t capacity,
+                            uint32_t max_desc = 0);
+
+// Stage 1 (steps a1-a2): encode, sort by (segment, length, residues), bucket
+// bounds and gather into sorted records / bit masks.  Writes srec (n), speq
+// (n) and off (n_seg * 64 + 1) -- the pipeline's own buffers unless other
+// outputs are given.  Uses pl.rec/key/val/tmp as scratch.
+struct SetOut {
+  SeqRec* srec = nullptr;
+  PeqRec* speq = nullptr;
+  uint32_t* off = nullptr;
+};
+void stage_prepare(Pipeline& pl, const char* d_data, const uint64_t* d_off, uint32_t n, const uint32_t* d_segoff,
+                   uint32_t n_seg, uint32_t id_base, uint32_t id_tag, const SetOut& out, hipStream_t st);
+// The same from records already encoded (ids kept): sorts n records of `rec`.
+void stage_prepare_records(Pipeline& pl, const SeqRec* rec, uint32_t n, const SetOut& out, hipStream_t st);
+
+// Stage 2 (steps a3-a6): plan the parts and run the pair kernel into
+// pl.edges (capacity edges).  Resets the work counters (not the input error).
+void stage_pairs(Pipeline& pl, const PlanPart* d_parts, uint32_t n_parts, const PlanPart& inline_part, int k,
+                 const Sched& sched, uint64_t capacity, uint32_t grid_blocks, hipStream_t st, hipEvent_t ev0,
+                 hipEvent_t ev1);
+
+// Stage 3 (steps a7-a8): canonical sorted pairs into d_pairs; mode 0 adds
+// both ends to deg, mode 1 (query tag first) adds the first end.
+void stage_canon(Pipeline& pl, int mode, int shift, uint64_t capacity, uint32_t* d_pairs, int32_t* d_deg,
+                 hipStream_t st);
 
 // Enqueue the whole build on `st` with no host synchronisation.  ev0/ev1 (may
 // be NULL) bracket the pair kernel.

@@ -48,7 +48,26 @@ __global__ void k_unpack(const uint64_t* __restrict__ keys, uint64_t E_max,
   }
 }
 
+__global__ void k_insert_degrees(const uint32_t* __restrict__ pairs, const unsigned long long* __restrict__ dE,
+                                 uint64_t E_max, uint32_t n_old, int32_t* __restrict__ counts,
+                                 int32_t* __restrict__ deg) {
+  const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= eff_n(E_max, dE)) return;
+  const uint2 p = reinterpret_cast<const uint2*>(pairs)[e];
+  atomicAdd(&deg[p.x], 1);
+  atomicAdd(&deg[p.y], 1);
+  if (p.x >= n_old) atomicAdd(&counts[p.x - n_old], 1);
+  if (p.y >= n_old) atomicAdd(&counts[p.y - n_old], 1);
+}
+
 }  // namespace
+
+void launch_insert_degrees(const uint32_t* pairs, const unsigned long long* dE, uint64_t E_max, uint32_t n_old,
+                           int32_t* counts, int32_t* deg, hipStream_t st) {
+  if (E_max == 0) return;
+  hipLaunchKernelGGL(k_insert_degrees, dim3((uint32_t)((E_max + 255) / 256)), dim3(256), 0, st, pairs, dE, E_max,
+                     n_old, counts, deg);
+}
 
 void launch_edge_keys(const uint32_t* edges, uint64_t E_max, const unsigned long long* dE, int mode, int shift,
                       uint64_t* keys, hipStream_t st) {

@@ -34,6 +34,30 @@ __global__ void k_reset_counters(Counters* c) {
   }
 }
 
+__global__ void k_reset_work(Counters* c) {
+  if (threadIdx.x == 0) {
+    c->item_next = 0;
+    c->edges = 0;
+  }
+}
+
+__global__ void k_record_keys(const SeqRec* __restrict__ rec, uint32_t n, int nres, int len_shift,
+                              uint64_t* __restrict__ key, uint32_t* __restrict__ val) {
+  const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const SeqRec r = rec[i];
+  uint64_t lex = 0;
+#pragma unroll
+  for (int q = 0; q < 12; ++q) {
+    if (q < nres) {
+      const uint32_t c = q < (int)r.len ? (r.w[q / 6] >> (5 * (q % 6))) & 31u : 0u;
+      lex |= (uint64_t)c << (5 * (nres - 1 - q));
+    }
+  }
+  key[i] = ((uint64_t)r.len << len_shift) | lex;
+  val[i] = i;
+}
+
 __global__ void k_encode(const char* __restrict__ data, const uint64_t* __restrict__ off, uint32_t n,
                          const uint32_t* __restrict__ seg_off, uint32_t n_seg, int nres, int len_shift,
                          int seg_shift, uint32_t id_base, uint32_t id_tag, SeqRec* __restrict__ rec,
@@ -117,43 +141,95 @@ __global__ void k_gather(const SeqRec* __restrict__ rec, const uint32_t* __restr
   speq[s] = p;
 }
 
-// One thread block.  Entries (segment, m, delta) in segment-major order;
-// delta = 0 entries are split into row blocks of texts_per_item patterns so
-// that every work item of the triangle holds at least one valid pair.
+// One thread block plans every part.  Entries:
+//   self part:  (segment, m, delta) with n = m - delta, 0 <= delta <= k;
+//               delta = 0 entries are split into row blocks of texts_per_item
+//               patterns so that every work item of a triangle holds at least
+//               one valid pair;
+//   cross part: (La, Lb) with |La - Lb| <= k; the longer length supplies the
+//               patterns (set a when equal).
 constexpr int kPlanThreads = 1024;
 
-__device__ void entry_shape(const uint32_t* off, uint32_t e, int k, uint32_t T, uint32_t& seg, uint32_t& m,
-                            uint32_t& n, uint32_t& np, uint32_t& nt, uint32_t& ndesc, uint64_t& items,
-                            uint64_t& pairs) {
-  const uint32_t per_seg = 32u * (uint32_t)(k + 1);
-  seg = e / per_seg;
-  const uint32_t rem = e - seg * per_seg;
-  m = 1 + rem / (uint32_t)(k + 1);
-  const uint32_t delta = rem % (uint32_t)(k + 1);
-  ndesc = 0;
-  items = 0;
-  pairs = 0;
-  np = nt = 0;
-  if (delta >= m) return;
-  n = m - delta;
-  const uint32_t cm = seg * 64 + m, cn = seg * 64 + n;
-  np = off[cm + 1] - off[cm];
-  nt = off[cn + 1] - off[cn];
-  if (delta > 0) {
-    if (np == 0 || nt == 0) return;
-    ndesc = 1;
-    items = (uint64_t)((np + 63) / 64) * ((nt + T - 1) / T);
-    pairs = (uint64_t)np * nt;
-  } else {
-    if (np < 2) return;
-    ndesc = (np - 1 + T - 1) / T;  // row blocks b with b*T <= np-2
-    for (uint32_t bk = 0; bk < ndesc; ++bk) {
-      const uint32_t rows = min(T, np - bk * T);
-      const uint32_t cols = np - bk * T;
-      items += (uint64_t)((rows + 63) / 64) * ((cols + T - 1) / T);
+__device__ uint32_t part_entries(const PlanPart& p, int k) {
+  return p.cross ? 32u * (uint32_t)(2 * k + 1) : p.a.n_seg * 32u * (uint32_t)(k + 1);
+}
+
+struct Entry {
+  const SeqRec* prec;
+  const PeqRec* ppeq;
+  const SeqRec* trec;
+  uint32_t p0, np, t0, nt, m, n, tri, ndesc;
+  uint64_t items, pairs;
+};
+
+__device__ Entry entry_shape(const PlanPart& part, uint32_t e, int k, uint32_t T) {
+  Entry r;
+  r.ndesc = 0;
+  r.items = 0;
+  r.pairs = 0;
+  r.tri = 0;
+  r.np = r.nt = 0;
+  r.p0 = r.t0 = 0;
+  r.m = r.n = 0;
+  r.prec = part.a.srec;
+  r.ppeq = part.a.speq;
+  r.trec = part.a.srec;
+  if (!part.cross) {
+    const uint32_t per_seg = 32u * (uint32_t)(k + 1);
+    const uint32_t seg = e / per_seg;
+    const uint32_t rem = e - seg * per_seg;
+    const uint32_t m = 1 + rem / (uint32_t)(k + 1);
+    const uint32_t delta = rem % (uint32_t)(k + 1);
+    if (delta >= m) return r;
+    const uint32_t n = m - delta;
+    const uint32_t* off = part.a.off;
+    const uint32_t cm = seg * 64 + m, cn = seg * 64 + n;
+    r.m = m;
+    r.n = n;
+    r.p0 = off[cm];
+    r.np = off[cm + 1] - off[cm];
+    r.t0 = off[cn];
+    r.nt = off[cn + 1] - off[cn];
+    if (delta > 0) {
+      if (r.np == 0 || r.nt == 0) return r;
+      r.ndesc = 1;
+      r.items = (uint64_t)((r.np + 63) / 64) * ((r.nt + T - 1) / T);
+      r.pairs = (uint64_t)r.np * r.nt;
+    } else {
+      if (r.np < 2) return r;
+      r.tri = 1;
+      r.ndesc = (r.np - 1 + T - 1) / T;  // row blocks b with b*T <= np-2
+      for (uint32_t bk = 0; bk < r.ndesc; ++bk) {
+        const uint32_t rows = min(T, r.np - bk * T);
+        const uint32_t cols = r.np - bk * T;
+        r.items += (uint64_t)((rows + 63) / 64) * ((cols + T - 1) / T);
+      }
+      r.pairs = (uint64_t)r.np * (r.np - 1) / 2;
     }
-    pairs = (uint64_t)np * (np - 1) / 2;
+  } else {
+    const uint32_t span = (uint32_t)(2 * k + 1);
+    const uint32_t La = 1 + e / span;
+    const int Lb = (int)La + (int)(e % span) - k;
+    if (Lb < 1 || Lb > kMaxLen) return r;
+    const uint32_t na = part.a.off[La + 1] - part.a.off[La];
+    const uint32_t nb = part.b.off[Lb + 1] - part.b.off[Lb];
+    if (na == 0 || nb == 0) return r;
+    if ((int)La >= Lb) {
+      r.m = La; r.n = (uint32_t)Lb;
+      r.p0 = part.a.off[La]; r.np = na;
+      r.t0 = part.b.off[Lb]; r.nt = nb;
+      r.prec = part.a.srec; r.ppeq = part.a.speq; r.trec = part.b.srec;
+    } else {
+      r.m = (uint32_t)Lb; r.n = La;
+      r.p0 = part.b.off[Lb]; r.np = nb;
+      r.t0 = part.a.off[La]; r.nt = na;
+      r.prec = part.b.srec; r.ppeq = part.b.speq; r.trec = part.a.srec;
+    }
+    r.ndesc = 1;
+    r.items = (uint64_t)((r.np + 63) / 64) * ((r.nt + T - 1) / T);
+    r.pairs = (uint64_t)na * nb;
   }
+  return r;
 }
 
 __device__ uint64_t block_excl_scan_u64(uint64_t v, uint64_t* sh, uint64_t& total) {
@@ -172,59 +248,72 @@ __device__ uint64_t block_excl_scan_u64(uint64_t v, uint64_t* sh, uint64_t& tota
   return r;
 }
 
-__global__ __launch_bounds__(kPlanThreads) void k_plan(const uint32_t* __restrict__ off, uint32_t n_seg, int k,
-                                                       uint32_t T, Desc* __restrict__ descs,
-                                                       uint64_t* __restrict__ item_base, uint32_t max_desc,
-                                                       Plan* plan) {
+__global__ __launch_bounds__(kPlanThreads) void k_plan(const PlanPart* __restrict__ parts, uint32_t n_parts,
+                                                       PlanPart inline_part, int k, uint32_t T,
+                                                       Desc* __restrict__ descs, uint64_t* __restrict__ item_base,
+                                                       uint32_t max_desc, Plan* plan) {
   __shared__ uint64_t sh[kPlanThreads];
-  const uint32_t n_entries = n_seg * 32u * (uint32_t)(k + 1);
+  if (!parts) {
+    parts = nullptr;
+    n_parts = 1;
+  }
   uint64_t run_desc = 0, run_items = 0, run_pairs = 0;
-  for (uint32_t e0 = 0; e0 < n_entries; e0 += kPlanThreads) {
-    const uint32_t e = e0 + threadIdx.x;
-    uint32_t seg = 0, m = 0, n = 0, np = 0, nt = 0, nd = 0;
-    uint64_t items = 0, pairs = 0;
-    if (e < n_entries) entry_shape(off, e, k, T, seg, m, n, np, nt, nd, items, pairs);
-    uint64_t tot_d, tot_i, tot_p;
-    const uint64_t dpos = run_desc + block_excl_scan_u64(nd, sh, tot_d);
-    const uint64_t ipos = run_items + block_excl_scan_u64(items, sh, tot_i);
-    block_excl_scan_u64(pairs, sh, tot_p);
-    if (nd > 0 && dpos + nd <= max_desc) {
-      const uint32_t pm = off[seg * 64 + m], pn = off[seg * 64 + n];
-      if (m != n) {
+  for (uint32_t pi = 0; pi < n_parts; ++pi) {
+    const PlanPart part = parts ? parts[pi] : inline_part;
+    const uint32_t n_entries = part_entries(part, k);
+    for (uint32_t e0 = 0; e0 < n_entries; e0 += kPlanThreads) {
+      const uint32_t e = e0 + threadIdx.x;
+      Entry en;
+      en.ndesc = 0;
+      en.items = 0;
+      en.pairs = 0;
+      if (e < n_entries) en = entry_shape(part, e, k, T);
+      uint64_t tot_d, tot_i, tot_p;
+      const uint64_t dpos = run_desc + block_excl_scan_u64(en.ndesc, sh, tot_d);
+      const uint64_t ipos = run_items + block_excl_scan_u64(en.items, sh, tot_i);
+      block_excl_scan_u64(en.pairs, sh, tot_p);
+      if (en.ndesc > 0 && dpos + en.ndesc <= max_desc) {
         Desc d;
-        d.p0 = pm; d.np = np; d.t0 = pn; d.nt = nt; d.m = m; d.n = n; d.tri = 0;
-        d.chunks = (nt + T - 1) / T;
-        d.item_base = ipos;
-        d.items = items;
-        descs[dpos] = d;
-        item_base[dpos] = ipos;
-      } else {
-        uint64_t ib = ipos;
-        for (uint32_t bk = 0; bk < nd; ++bk) {
-          Desc d;
-          const uint32_t rows = min(T, np - bk * T);
-          d.p0 = pm + bk * T; d.np = rows;
-          d.t0 = pm + bk * T; d.nt = np - bk * T;
-          d.m = m; d.n = n; d.tri = 1;
-          d.chunks = (d.nt + T - 1) / T;
-          d.item_base = ib;
-          d.items = (uint64_t)((rows + 63) / 64) * d.chunks;
-          descs[dpos + bk] = d;
-          item_base[dpos + bk] = ib;
-          ib += d.items;
+        d.prec = en.prec;
+        d.ppeq = en.ppeq;
+        d.trec = en.trec;
+        d.m = en.m;
+        d.n = en.n;
+        d.tri = en.tri;
+        if (!en.tri) {
+          d.p0 = en.p0; d.np = en.np; d.t0 = en.t0; d.nt = en.nt;
+          d.chunks = (en.nt + T - 1) / T;
+          d.item_base = ipos;
+          d.items = en.items;
+          descs[dpos] = d;
+          item_base[dpos] = ipos;
+        } else {
+          uint64_t ib = ipos;
+          for (uint32_t bk = 0; bk < en.ndesc; ++bk) {
+            const uint32_t rows = min(T, en.np - bk * T);
+            d.p0 = en.p0 + bk * T; d.np = rows;
+            d.t0 = en.p0 + bk * T; d.nt = en.np - bk * T;
+            d.chunks = (d.nt + T - 1) / T;
+            d.item_base = ib;
+            d.items = (uint64_t)((rows + 63) / 64) * d.chunks;
+            descs[dpos + bk] = d;
+            item_base[dpos + bk] = ib;
+            ib += d.items;
+          }
         }
       }
+      run_desc += tot_d;
+      run_items += tot_i;
+      run_pairs += tot_p;
     }
-    run_desc += tot_d;
-    run_items += tot_i;
-    run_pairs += tot_p;
   }
   if (threadIdx.x == 0) {
     Plan p;
-    p.total_items = run_desc <= max_desc ? run_items : 0;
+    const bool ok = run_desc <= max_desc;
+    p.total_items = ok ? run_items : 0;
     p.evaluated_pairs = run_pairs;
-    p.n_desc = (uint32_t)(run_desc <= max_desc ? run_desc : 0);
-    p.pad = run_desc <= max_desc ? 0u : 1u;  // 1: descriptor overflow
+    p.n_desc = (uint32_t)(ok ? run_desc : 0);
+    p.pad = ok ? 0u : 1u;  // 1: descriptor overflow
     *plan = p;
   }
 }
@@ -244,6 +333,10 @@ void launch_reset_counters(Counters* c, hipStream_t st) {
   hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, st, c);
 }
 
+void launch_reset_work(Counters* c, hipStream_t st) {
+  hipLaunchKernelGGL(k_reset_work, dim3(1), dim3(64), 0, st, c);
+}
+
 static int encode_nres(uint32_t seg_bits) { return (int)((58 - seg_bits) / 5); }
 int encode_key_bits(uint32_t seg_bits) { return (int)seg_bits + 6 + 5 * encode_nres(seg_bits); }
 int encode_combo_shift(uint32_t seg_bits) { return 5 * encode_nres(seg_bits); }
@@ -259,6 +352,12 @@ void launch_encode(const char* d_data, const uint64_t* d_off, uint32_t n, const 
                      nres, len_shift, seg_shift, id_base, id_tag, rec, key, val, cnt);
 }
 
+void launch_record_keys(const SeqRec* rec, uint32_t n, uint64_t* key, uint32_t* val, hipStream_t st) {
+  if (n == 0) return;
+  const int nres = encode_nres(0);
+  hipLaunchKernelGGL(k_record_keys, dim3(blocks_for(n, 256)), dim3(256), 0, st, rec, n, nres, 5 * nres, key, val);
+}
+
 void launch_bucket_bounds(const uint64_t* key, uint64_t n, int combo_shift, uint32_t n_combo, uint32_t* off,
                           hipStream_t st) {
   hipLaunchKernelGGL(k_bounds, dim3(blocks_for(n + 1, 256)), dim3(256), 0, st, key, n, combo_shift, n_combo,
@@ -271,17 +370,19 @@ void launch_gather(const SeqRec* rec, const uint32_t* val, uint64_t n, SeqRec* s
   hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, 256)), dim3(256), 0, st, rec, val, n, srec, speq);
 }
 
-uint32_t plan_max_desc(uint32_t n_seg, const uint32_t*, int k, uint32_t T, uint64_t n) {
+uint32_t plan_max_desc_self(uint32_t n_seg, int k, uint32_t T, uint64_t n) {
   // rectangles: one per (segment, m, delta>0); triangles: sum over buckets of
   // ceil((np-1)/T) <= n/T + 32 per segment
   uint64_t v = (uint64_t)n_seg * 32u * (uint32_t)(k + 1) + n / T + (uint64_t)n_seg * 32u + 1;
   return (uint32_t)v;
 }
 
-void launch_plan(const uint32_t* off, uint32_t n_seg, int k, uint32_t T, Desc* descs, uint64_t* item_base,
-                 uint32_t max_desc, Plan* plan, hipStream_t st) {
-  hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, st, off, n_seg, k, T, descs, item_base, max_desc,
-                     plan);
+uint32_t plan_max_desc_cross(int k) { return 32u * (uint32_t)(2 * k + 1); }
+
+void launch_plan(const PlanPart* d_parts, uint32_t n_parts, const PlanPart& inline_part, int k, uint32_t T,
+                 Desc* descs, uint64_t* item_base, uint32_t max_desc, Plan* plan, hipStream_t st) {
+  hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, st, d_parts, n_parts, inline_part, k, T, descs,
+                     item_base, max_desc, plan);
 }
 
 }  // namespace tcr
