@@ -10,6 +10,7 @@ Contents
              (paper, Methods: "Levenshtein distance", "TCR network",
              "Adjacency matrix", "Overview of network theory concepts")
   k1.c       an independent closed-form witness for threshold 1 (no DP)
+  graph.c    breadth-first connected components and site percolation
   checks.py  pure-Python brute force over the edit graph on tiny alphabets
 
 ``build_lib()`` compiles both C files into ``liboracle.so`` with gcc.
@@ -24,7 +25,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
-SOURCES = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "k1.c")]
+SOURCES = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "k1.c"), os.path.join(_HERE, "graph.c")]
 
 
 def build_lib(out: str = LIB_PATH, extra_flags=()) -> str:
@@ -72,6 +73,12 @@ def _bind(lib):
     lib.k1_adjacent.argtypes = [_u8p, ctypes.c_int, _u8p, ctypes.c_int]
     lib.k1_free.restype = None
     lib.k1_free.argtypes = [ctypes.c_void_p]
+    lib.oracle_components.restype = ctypes.c_int64
+    lib.oracle_components.argtypes = [_u8p, ctypes.c_uint64, ctypes.c_uint32, ctypes.c_void_p, ctypes.c_void_p,
+                                      ctypes.c_void_p]
+    lib.oracle_robustness.restype = ctypes.c_int
+    lib.oracle_robustness.argtypes = [_u8p, ctypes.c_uint64, ctypes.c_uint32, _u8p, _u8p, ctypes.c_uint32,
+                                      ctypes.c_void_p]
     return lib
 
 
@@ -189,3 +196,51 @@ class Oracle:
     def k1_adjacent(self, a, b) -> bool:
         a, b = _as_bytes(a), _as_bytes(b)
         return bool(self.lib.k1_adjacent(a, len(a), b, len(b)))
+
+
+def _pairs_arg(pairs):
+    p = np.ascontiguousarray(np.asarray(pairs, dtype=np.uint32).reshape(-1, 2))
+    return p if p.size else np.zeros((1, 2), dtype=np.uint32), int(len(np.asarray(pairs).reshape(-1, 2)))
+
+
+def components(pairs, n: int):
+    """(labels, sizes, n_components, lcc): labels[i] = smallest id of i's
+    component; sizes[i] = size of the component labelled i (0 if none)."""
+    lib = load()
+    p, E = _pairs_arg(pairs)
+    labels = np.zeros(max(1, n), dtype=np.uint32)
+    sizes = np.zeros(max(1, n), dtype=np.uint32)
+    nc = ctypes.c_uint32()
+    lcc = lib.oracle_components(p.ctypes.data, E, n, labels.ctypes.data, sizes.ctypes.data, ctypes.byref(nc))
+    if lcc < 0:
+        raise MemoryError("oracle_components failed")
+    return labels[:n], sizes[:n], nc.value, int(lcc)
+
+
+def robustness(pairs, n: int, order, removed):
+    """LCC size after removing order[:r] for each r in removed."""
+    lib = load()
+    p, E = _pairs_arg(pairs)
+    order = np.ascontiguousarray(order, dtype=np.uint32)
+    removed = np.ascontiguousarray(removed, dtype=np.uint32)
+    out = np.zeros(max(1, len(removed)), dtype=np.uint32)
+    rc = lib.oracle_robustness(p.ctypes.data, E, n, order.ctypes.data if n else None, removed.ctypes.data,
+                               len(removed), out.ctypes.data)
+    if rc != 0:
+        raise MemoryError("oracle_robustness failed")
+    return out[:len(removed)]
+
+
+def lcc_norm1(lcc, removed, n: int):
+    """Paper, Methods, "Computing LCC": LCC(p) / ((1 - p) N), p = removed / N."""
+    lcc = np.asarray(lcc, dtype=np.float64)
+    alive = n - np.asarray(removed, dtype=np.float64)
+    return np.where(alive > 0, lcc / np.maximum(alive, 1), 0.0)
+
+
+def lcc_norm2(lcc, removed, n: int):
+    """LCC_norm,1(p) / LCC_norm,1(0); removed[0] must be 0."""
+    r = np.asarray(removed)
+    assert r[0] == 0
+    v = lcc_norm1(lcc, removed, n)
+    return v / v[0] if v[0] > 0 else v
