@@ -244,3 +244,33 @@ def lcc_norm2(lcc, removed, n: int):
     assert r[0] == 0
     v = lcc_norm1(lcc, removed, n)
     return v / v[0] if v[0] > 0 else v
+
+
+def graph_stats(pairs, n: int, hist_len: int | None = None):
+    """Degree statistics, assortativity and clustering (see graph.c)."""
+    lib = load()
+    if not hasattr(lib, "_stats_bound"):
+        lib.oracle_graph_stats.restype = ctypes.c_int64
+        lib.oracle_graph_stats.argtypes = [_u8p, ctypes.c_uint64, ctypes.c_uint32] + [ctypes.c_void_p] * 3 + \
+            [ctypes.c_uint32] + [ctypes.c_void_p] * 5
+        lib._stats_bound = True
+    p, E = _pairs_arg(pairs)
+    hist_len = hist_len or (n + 1)
+    deg = np.zeros(max(1, n), dtype=np.int32)
+    cnt = np.zeros(max(1, hist_len), dtype=np.uint64)
+    nbr = np.zeros(max(1, hist_len), dtype=np.uint64)
+    tri = np.zeros(max(1, n), dtype=np.uint64)
+    clu = np.zeros(max(1, n), dtype=np.float64)
+    r = ctypes.c_double()
+    avg = ctypes.c_double()
+    t3 = ctypes.c_uint64()
+    maxd = lib.oracle_graph_stats(p.ctypes.data, E, n, deg.ctypes.data, cnt.ctypes.data, nbr.ctypes.data, hist_len,
+                                  tri.ctypes.data, clu.ctypes.data, ctypes.byref(r), ctypes.byref(avg),
+                                  ctypes.byref(t3))
+    if maxd == -1:
+        raise MemoryError("oracle_graph_stats failed")
+    if maxd == -2:
+        raise ValueError("hist_len too small")
+    return {"degree": deg[:n], "max_degree": int(maxd), "count": cnt[:maxd + 1], "nbr_sum": nbr[:maxd + 1],
+            "triangles_per_node": tri[:n], "clustering": clu[:n], "assortativity": r.value,
+            "avg_clustering": avg.value, "triangles": t3.value}

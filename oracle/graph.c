@@ -136,3 +136,91 @@ int oracle_robustness(const uint32_t* pairs, uint64_t E, uint32_t n, const uint3
   free(g.adj);
   return rc;
 }
+
+/*
+ * Degree statistics of a simple undirected graph given as distinct pairs
+ * (paper, Methods, "Overview of network theory concepts": degree d(u), degree
+ * distribution p_d, average neighbour degree <d_nn>, degree assortativity r
+ * (Newman 2002), and the clustering coefficient used in Results, "Network
+ * structure of TCR repertoires").  Plain definitions:
+ *   degree[u]       = number of pairs naming u
+ *   count[d]        = number of nodes of degree d                 (hist_len)
+ *   nbr_sum[d]      = sum over nodes u of degree d of the degrees of u's
+ *                     neighbours; <d_nn>(d) = nbr_sum[d] / (d * count[d])
+ *   r               = Pearson correlation of the degrees at the two ends of
+ *                     an edge, over both orientations of every edge
+ *   tri[u]          = triangles through u (pairs of neighbours that are
+ *                     adjacent), clustering[u] = 2 tri[u] / (d (d - 1)), 0
+ *                     for d < 2; avg_clustering = mean over all nodes
+ * Returns the maximum degree, or -1 on allocation failure, -2 if hist_len
+ * is too small (count/nbr_sum then untouched).
+ */
+int64_t oracle_graph_stats(const uint32_t* pairs, uint64_t E, uint32_t n, int32_t* degree, uint64_t* count,
+                           uint64_t* nbr_sum, uint32_t hist_len, uint64_t* tri, double* clustering, double* r_out,
+                           double* avg_clustering, uint64_t* triangles) {
+  csr g;
+  if (build_csr(pairs, E, n, &g)) return -1;
+  int64_t maxd = 0;
+  for (uint32_t u = 0; u < n; ++u) {
+    int64_t d = (int64_t)(g.start[u + 1] - g.start[u]);
+    if (degree) degree[u] = (int32_t)d;
+    if (d > maxd) maxd = d;
+  }
+  if ((uint64_t)maxd >= hist_len) {
+    free(g.start);
+    free(g.adj);
+    return -2;
+  }
+  memset(count, 0, sizeof(uint64_t) * hist_len);
+  memset(nbr_sum, 0, sizeof(uint64_t) * hist_len);
+  for (uint32_t u = 0; u < n; ++u) {
+    uint64_t d = g.start[u + 1] - g.start[u];
+    count[d]++;
+    for (uint64_t q = g.start[u]; q < g.start[u + 1]; ++q) {
+      uint32_t v = g.adj[q];
+      nbr_sum[d] += g.start[v + 1] - g.start[v];
+    }
+  }
+  /* assortativity over both orientations of every edge */
+  double sx = 0, sxx = 0, sxy = 0, m2 = 0;
+  for (uint64_t e = 0; e < E; ++e) {
+    double a = (double)(g.start[pairs[2 * e] + 1] - g.start[pairs[2 * e]]);
+    double b = (double)(g.start[pairs[2 * e + 1] + 1] - g.start[pairs[2 * e + 1]]);
+    sx += a + b;
+    sxx += a * a + b * b;
+    sxy += 2 * a * b;
+    m2 += 2;
+  }
+  if (r_out) {
+    double mean = m2 > 0 ? sx / m2 : 0;
+    double var = m2 > 0 ? sxx / m2 - mean * mean : 0;
+    *r_out = var > 0 ? (sxy / m2 - mean * mean) / var : 0.0;
+  }
+  /* triangles: neighbours v < w of u that are adjacent (adjacency test by a
+     scan of v's list) */
+  uint64_t total3 = 0;
+  double csum = 0;
+  for (uint32_t u = 0; u < n; ++u) {
+    uint64_t t = 0;
+    for (uint64_t a = g.start[u]; a < g.start[u + 1]; ++a)
+      for (uint64_t b = a + 1; b < g.start[u + 1]; ++b) {
+        uint32_t v = g.adj[a], w = g.adj[b];
+        for (uint64_t q = g.start[v]; q < g.start[v + 1]; ++q)
+          if (g.adj[q] == w) {
+            ++t;
+            break;
+          }
+      }
+    if (tri) tri[u] = t;
+    total3 += t;
+    uint64_t d = g.start[u + 1] - g.start[u];
+    double c = d >= 2 ? 2.0 * (double)t / ((double)d * (double)(d - 1)) : 0.0;
+    if (clustering) clustering[u] = c;
+    csum += c;
+  }
+  if (avg_clustering) *avg_clustering = n ? csum / n : 0.0;
+  if (triangles) *triangles = total3 / 3;
+  free(g.start);
+  free(g.adj);
+  return maxd;
+}

@@ -84,3 +84,41 @@ def test_lcc_normalisations():
     removed = [0, 20, 90]
     assert np.allclose(oracle.lcc_norm1(lcc, removed, n), [0.8, 0.75, 1.0])
     assert np.allclose(oracle.lcc_norm2(lcc, removed, n), [1.0, 0.75 / 0.8, 1.0 / 0.8])
+
+
+@pytest.mark.parametrize("seed", [4, 5])
+def test_graph_stats_against_networkx(seed):
+    n = 400
+    G = nx.gnp_random_graph(n, 4.0 / n, seed=seed)
+    # add a few triangles and a hub
+    G.add_edges_from([(0, 1), (1, 2), (0, 2), (5, 6), (6, 7), (5, 7), (5, 8), (7, 8)])
+    G.add_edges_from((9, v) for v in range(10, 60))
+    pairs = np.array(sorted(tuple(sorted(e)) for e in G.edges()), dtype=np.uint32)
+    st = oracle.graph_stats(pairs, n)
+    deg = np.array([G.degree(i) for i in range(n)])
+    assert np.array_equal(st["degree"], deg)
+    assert st["count"].tolist() == nx.degree_histogram(G)
+    knn = nx.average_degree_connectivity(G)
+    for d, v in knn.items():
+        if d == 0:
+            continue
+        assert st["nbr_sum"][d] / (d * st["count"][d]) == pytest.approx(v, rel=1e-12)
+    assert st["assortativity"] == pytest.approx(nx.degree_assortativity_coefficient(G), rel=1e-9, abs=1e-12)
+    cl = nx.clustering(G)
+    assert np.allclose(st["clustering"], [cl[i] for i in range(n)], rtol=0, atol=1e-15)
+    assert st["avg_clustering"] == pytest.approx(nx.average_clustering(G), rel=1e-12)
+    tri = nx.triangles(G)
+    assert st["triangles_per_node"].tolist() == [tri[i] for i in range(n)]
+    assert st["triangles"] == sum(tri.values()) // 3
+
+
+def test_graph_stats_paper_example():
+    st = oracle.graph_stats([[0, 1], [0, 2], [1, 4], [3, 4]], 5)
+    assert st["degree"].tolist() == [2, 2, 1, 1, 2]
+    assert st["count"].tolist() == [0, 2, 3]
+    # <d_nn>(1) = (deg 2 + deg 2) / 2 ; <d_nn>(2) = (2+1 + 2+2 + 2+1) / (2*3)
+    assert st["nbr_sum"].tolist() == [0, 4, 10]
+    assert st["triangles"] == 0 and st["avg_clustering"] == 0.0
+    # triangle graph: clustering 1 everywhere, assortativity undefined -> 0
+    st = oracle.graph_stats([[0, 1], [0, 2], [1, 2]], 3)
+    assert st["clustering"].tolist() == [1.0, 1.0, 1.0] and st["triangles"] == 1
