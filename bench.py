@@ -178,6 +178,45 @@ def serve_leg(tn, ctx, rep, n_requests: int, log) -> dict:
             "resident_start": rep.n, "resident_end": final, "index_k": 1}
 
 
+def host_to_host(tn, ctx, seqs, k) -> dict:
+    """One build from host strings to host edges and degrees (PCIe copies
+    and the host-side validation included)."""
+    tn.tcrnet_build(ctx, seqs, k)
+    t0 = time.perf_counter()
+    g = tn.tcrnet_build(ctx, seqs, k)
+    dt = time.perf_counter() - t0
+    n = seqs.n
+    return {"ms": dt * 1e3, "pairs_per_s": n * (n - 1) // 2 / dt, "edges": int(len(g.pairs))}
+
+
+def analysis_leg(tn, ctx, seqs, k) -> dict:
+    """Network analysis of the built network: components/LCC, the site-
+    percolation curve at 21 removal fractions, degree statistics (host edge
+    list in, host results out)."""
+    g = tn.tcrnet_build(ctx, seqs, k)
+    n = seqs.n
+    out = {"edges": int(len(g.pairs))}
+    tn.tcrnet_components(ctx, g.pairs, n)
+    t0 = time.perf_counter()
+    labels, sizes, nc, lcc = tn.tcrnet_components(ctx, g.pairs, n)
+    out["components_ms"] = (time.perf_counter() - t0) * 1e3
+    out["n_components"], out["lcc"] = int(nc), int(lcc)
+    order = np.random.default_rng(20211215).permutation(n).astype(np.uint32)   # random removal order
+    removed = np.round(np.linspace(0.0, 1.0, 21) * n).astype(np.uint32)
+    t0 = time.perf_counter()
+    curve = tn.tcrnet_robustness(ctx, g.pairs, n, order, removed)
+    out["robustness_ms"] = (time.perf_counter() - t0) * 1e3
+    out["lcc_norm2"] = [round(float(x), 6) for x in tn.lcc_norm2(curve, removed, n)]
+    t0 = time.perf_counter()
+    st = tn.tcrnet_graph_stats(ctx, g.pairs, n)
+    out["graph_stats_ms"] = (time.perf_counter() - t0) * 1e3
+    out["max_degree"] = int(st["max_degree"])
+    out["triangles"] = int(st["triangles"])
+    out["assortativity"] = float(st["assortativity"])
+    out["avg_clustering"] = float(st["avg_clustering"])
+    return out
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,6 +227,7 @@ def main():
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
     ap.add_argument("--autotune", action="store_true")
+    ap.add_argument("--no-analysis", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=400)
     ap.add_argument("--calib-copy-mib", type=int, default=0,
                     help="run one device copy of this size first (HBM counter calibration)")
@@ -224,6 +264,8 @@ def main():
     ctx = tn.Context(0)
     if args.autotune:
         tn.tcrnet_autotune(ctx, seqs, k)
+    peak_meas, peak_s = tn.tcrnet_valu_peak(ctx)
+    log(f"measured VALU issue rate {peak_meas / 1e12:.2f} T lane-instr/s ({peak_s * 1e3:.1f} ms probe)")
     step_s, E, infos = plain_build(tn, torch, seqs, k, args.steps, args.warmup, ctx)
     pk_ms = float(np.mean([i["pair_kernel_ms"] for i in infos]))
     assert all(i["evaluated_pairs"] == ev_pairs for i in infos)
@@ -263,8 +305,15 @@ def main():
             "work_per_unit": f"{T_STEP_INSTR} x {model['mean_exit_steps']:.4f} VALU instr per evaluated pair",
             "units_per_launch": ev_pairs,
             "frac_logical_17op": achieved / PEAK_LANE_OPS * T_STEP_LOGICAL / T_STEP_INSTR,
+            "peak_measured": peak_meas / 1e12,
+            "frac_of_measured": achieved / peak_meas,
         },
     }
+    log("host-to-host build ...")
+    out["host_to_host"] = host_to_host(tn, ctx, seqs, k)
+    if not args.no_analysis:
+        log("network analysis ...")
+        out["analysis"] = analysis_leg(tn, ctx, seqs, k)
     if not args.no_batch:
         log("batched form (256 repertoires) ...")
         out["batch"] = batch_leg(tn, ctx, synth.batch())

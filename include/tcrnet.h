@@ -127,6 +127,14 @@ TCRNET_API int32_t tcrnet_build_device(tcrnet_ctx* ctx, const char* d_data, cons
                                        uint32_t n, int32_t k, void* stream, uint32_t* d_pairs,
                                        uint64_t pair_capacity, int32_t* d_degree, uint64_t* n_edges);
 
+/* Multi-threshold build: every pair with lev <= k_max, with its exact
+ * distance (paper, Results, "LCC transition": networks for several l_max).
+ * The network at any k <= k_max is the set of edges with distance <= k.
+ * Degrees are those at k_max.  At most 2^29 sequences.  The distances are
+ * read with tcrnet_graph_distances. */
+TCRNET_API int32_t tcrnet_build_weighted(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k_max,
+                                         tcrnet_graph** out);
+
 /* Many independent repertoires (each its own network, own 0-based ids) in
  * one launch sequence: one persistent pair kernel over all repertoires' work
  * items, captured in a HIP graph.  outs[r] receives repertoire r's graph. */
@@ -136,6 +144,9 @@ TCRNET_API int32_t tcrnet_build_batch(tcrnet_ctx* ctx, const tcrnet_seqs* reps, 
 /* Host views of a graph (valid until tcrnet_graph_free). */
 TCRNET_API int32_t tcrnet_graph_edges(const tcrnet_graph* g, const uint32_t** pairs, uint64_t* n_edges);
 TCRNET_API int32_t tcrnet_graph_degree(const tcrnet_graph* g, const int32_t** degree, uint32_t* n);
+/* Edge distances (E bytes, aligned with the edge list) of a weighted build;
+   TCRNET_ESTATE for other graphs. */
+TCRNET_API int32_t tcrnet_graph_distances(const tcrnet_graph* g, const uint8_t** dist, uint64_t* n_edges);
 /* Counters of the build that made `g`: evaluated (length-compatible) pairs,
    pair-kernel time in milliseconds (HIP events around the pair kernel on its
    stream), whole-build time in ms (events around all device work), the
@@ -161,6 +172,19 @@ TCRNET_API void tcrnet_graph_free(tcrnet_graph* g);
  * fastest in the context for inputs of the same size class and k.  Results
  * are exact for every candidate; only speed differs. */
 TCRNET_API int32_t tcrnet_autotune(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k);
+
+/* ------------------------------------------------------------- diagnostics
+ * Measured 32-bit VALU issue rate of the context's device, in lane-
+ * instructions per second: eight waves per SIMD on every CU run independent
+ * chains of v_xor_b32 / v_add_u32 (plain 32-bit integer VALU instructions of
+ * the bit-vector step's kind) for a few tens of ms, timed with events on the
+ * context's stream.  On gfx950 two waves of a SIMD issue such instructions
+ * in the same 4-clock window, so their nominal peak is CUs x 128 lanes x
+ * clock; this call is its measured counterpart.
+ * *seconds (may be NULL) receives the timed duration.  Allocates and frees a
+ * 2 MB scratch buffer; errors: TCRNET_EINVAL (NULL ctx or rate pointer),
+ * TCRNET_EDEVICE. */
+TCRNET_API int32_t tcrnet_valu_peak(tcrnet_ctx* ctx, double* lane_instr_per_s, double* seconds);
 
 /* ------------------------------------------------------------------ serving
  * A resident repertoire on the device (sorted into length buckets), with its
@@ -207,6 +231,58 @@ TCRNET_API int32_t tcrnet_result_pairs(const tcrnet_result* r, const uint32_t** 
 TCRNET_API int32_t tcrnet_result_counts(const tcrnet_result* r, const int32_t** counts, uint32_t* n);
 TCRNET_API int32_t tcrnet_result_info_get(const tcrnet_result* r, tcrnet_result_info* info);
 TCRNET_API void tcrnet_result_free(tcrnet_result* r);
+
+/* ---------------------------------------------------------------- analysis
+ * Network analysis on an edge list of n nodes (host arrays; pairs may come
+ * from any build above).  Paper, Methods, "Overview of network theory
+ * concepts" (connected subgraphs, largest connected component, cluster
+ * sizes), "Percolation transition" (site percolation: node removal) and
+ * "Computing LCC" (LCC after removal).  Every pair must name nodes < n
+ * (else TCRNET_EINVAL); duplicate pairs and self loops are allowed. */
+typedef struct {
+  uint32_t n_components; /* number of connected components */
+  uint32_t lcc_size;     /* nodes in the largest one (0 when n = 0) */
+} tcrnet_cc_info;
+
+/* Components: labels[i] (n entries, may be NULL) = smallest node id of i's
+   component; sizes[i] (n entries, may be NULL) = size of the component whose
+   label is i, 0 if i is not a label.  The cluster-size distribution is the
+   histogram of the nonzero sizes. */
+TCRNET_API int32_t tcrnet_components(tcrnet_ctx* ctx, const uint32_t* pairs, uint64_t n_edges, uint32_t n,
+                                     uint32_t* labels, uint32_t* sizes, tcrnet_cc_info* info);
+
+/* Site percolation: order is a permutation of 0..n-1 (the random removal
+   order, drawn by the caller); for each q < n_runs the nodes
+   order[0 .. removed[q]) are removed (removed[q] <= n) and lcc[q] receives
+   the size of the largest connected component of the rest. */
+TCRNET_API int32_t tcrnet_robustness(tcrnet_ctx* ctx, const uint32_t* pairs, uint64_t n_edges, uint32_t n,
+                                     const uint32_t* order, const uint32_t* removed, uint32_t n_runs, uint32_t* lcc);
+
+/* Degree statistics of a canonical edge list (i < j, sorted by (i, j),
+   distinct: the output of the builds), paper, Methods, "Overview of network
+   theory concepts": degree d(u), degree distribution p_d, average neighbour
+   degree <d_nn>, degree assortativity r; Results: clustering coefficient.
+     degree[n]        d(u)                                      (may be NULL)
+     deg_count[h]     number of nodes with degree d, d < hist_len
+     nbr_deg_sum[h]   sum over nodes u of degree d of the degrees of u's
+                      neighbours, so <d_nn>(d) = nbr_deg_sum[d] / (d count[d])
+     clustering[n]    2 T(u) / (d (d - 1)), T(u) = triangles through u, 0 for
+                      d < 2                                     (may be NULL)
+   A maximum degree >= hist_len gives TCRNET_ETRUNC with out->max_degree set
+   (the histogram arrays then miss the larger degrees). */
+typedef struct {
+  uint32_t max_degree;
+  uint64_t triangles;
+  double assortativity;   /* Pearson correlation of the end degrees of edges */
+  double avg_clustering;  /* mean of clustering[] over all n nodes */
+  uint64_t sum_jk;        /* exact sums behind r over edges (j, k) */
+  uint64_t sum_j_plus_k;
+  uint64_t sum_j2_plus_k2;
+} tcrnet_stats;
+
+TCRNET_API int32_t tcrnet_graph_stats(tcrnet_ctx* ctx, const uint32_t* pairs, uint64_t n_edges, uint32_t n,
+                                      int32_t* degree, uint64_t* deg_count, uint64_t* nbr_deg_sum, uint32_t hist_len,
+                                      double* clustering, tcrnet_stats* out);
 
 #ifdef __cplusplus
 }

@@ -79,7 +79,10 @@ _SIGS = [
     ("tcrnet_graph_info", _I32, [_P, ctypes.POINTER(tcrnet_build_info)]),
     ("tcrnet_ctx_last_info", _I32, [_P, ctypes.POINTER(tcrnet_build_info)]),
     ("tcrnet_graph_free", None, [_P]),
+    ("tcrnet_build_weighted", _I32, [_P, ctypes.POINTER(tcrnet_seqs), _I32, _PP]),
+    ("tcrnet_graph_distances", _I32, [_P, _PP, _U64P]),
     ("tcrnet_autotune", _I32, [_P, ctypes.POINTER(tcrnet_seqs), _I32]),
+    ("tcrnet_valu_peak", _I32, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     ("tcrnet_index_create", _I32, [_P, ctypes.POINTER(tcrnet_seqs), _I32, _PP]),
     ("tcrnet_index_size", _I32, [_P, _U32P]),
     ("tcrnet_index_degree", _I32, [_P, _PP, _U32P]),
@@ -166,6 +169,13 @@ class Graph:
     pairs: np.ndarray           # (E, 2) uint32, i < j, sorted
     degree: np.ndarray          # (N,) int32
     info: dict = field(default_factory=dict)
+    dist: np.ndarray | None = None   # (E,) uint8 edge distances (weighted builds)
+
+    def at(self, k: int) -> np.ndarray:
+        """Edges of the network at threshold k <= k_max (weighted builds)."""
+        if self.dist is None:
+            raise ValueError("not a weighted build")
+        return self.pairs[self.dist <= k]
 
 
 def _info_dict(inf: tcrnet_build_info) -> dict:
@@ -186,8 +196,14 @@ def _take_graph(g) -> Graph:
            if nn.value else np.zeros(0, dtype=np.int32))
     inf = tcrnet_build_info()
     _check(_lib.tcrnet_graph_info(g, ctypes.byref(inf)))
+    dist = None
+    dp = ctypes.c_void_p()
+    dn = ctypes.c_uint64()
+    if _lib.tcrnet_graph_distances(g, ctypes.byref(dp), ctypes.byref(dn)) == TCRNET_OK:
+        dist = (np.ctypeslib.as_array(ctypes.cast(dp, ctypes.POINTER(ctypes.c_uint8)), shape=(dn.value,)).copy()
+                if dn.value else np.zeros(0, dtype=np.uint8))
     _lib.tcrnet_graph_free(g)
-    return Graph(pairs.reshape(-1, 2), deg, _info_dict(inf))
+    return Graph(pairs.reshape(-1, 2), deg, _info_dict(inf), dist)
 
 
 # ---------------------------------------------------------------- context
@@ -233,6 +249,15 @@ def tcrnet_build(ctx: Context, seqs, k: int) -> Graph:
     return _take_graph(g)
 
 
+def tcrnet_build_weighted(ctx: Context, seqs, k_max: int) -> Graph:
+    """All pairs with lev <= k_max and their distances (Graph.dist)."""
+    chars, offs = _as_seqs(seqs)
+    s = _c_seqs(chars, offs)
+    g = ctypes.c_void_p()
+    _check(_lib.tcrnet_build_weighted(ctx.handle, ctypes.byref(s), k_max, ctypes.byref(g)))
+    return _take_graph(g)
+
+
 def tcrnet_build_device(ctx: Context, d_chars, d_offsets, k: int, d_pairs, d_degree, stream=None) -> int:
     """Device-resident build.  d_chars: uint8 CUDA tensor; d_offsets: int64 CUDA
     tensor (n+1); d_pairs: int32/uint32-sized CUDA tensor of shape (cap, 2);
@@ -267,6 +292,14 @@ def tcrnet_autotune(ctx: Context, seqs, k: int) -> None:
     chars, offs = _as_seqs(seqs)
     s = _c_seqs(chars, offs)
     _check(_lib.tcrnet_autotune(ctx.handle, ctypes.byref(s), k))
+
+
+def tcrnet_valu_peak(ctx: Context) -> tuple[float, float]:
+    """Measured 32-bit VALU issue rate (lane-instructions/s) and the seconds
+    the probe ran."""
+    rate, sec = ctypes.c_double(), ctypes.c_double()
+    _check(_lib.tcrnet_valu_peak(ctx.handle, ctypes.byref(rate), ctypes.byref(sec)))
+    return rate.value, sec.value
 
 
 def version() -> str:
@@ -373,3 +406,94 @@ def tcrnet_wait(idx: Index, ticket: int) -> Result:
     r = ctypes.c_void_p()
     _check(_lib.tcrnet_wait(idx.handle, ticket, ctypes.byref(r)))
     return _take_result(r)
+
+
+# --------------------------------------------------------------- analysis
+class tcrnet_cc_info(ctypes.Structure):
+    _fields_ = [("n_components", ctypes.c_uint32), ("lcc_size", ctypes.c_uint32)]
+
+
+class tcrnet_stats(ctypes.Structure):
+    _fields_ = [("max_degree", ctypes.c_uint32), ("triangles", ctypes.c_uint64), ("assortativity", ctypes.c_double),
+                ("avg_clustering", ctypes.c_double), ("sum_jk", ctypes.c_uint64), ("sum_j_plus_k", ctypes.c_uint64),
+                ("sum_j2_plus_k2", ctypes.c_uint64)]
+
+
+_LATE = [
+    ("tcrnet_components", _I32, [_P, _P, ctypes.c_uint64, ctypes.c_uint32, _P, _P, ctypes.POINTER(tcrnet_cc_info)]),
+    ("tcrnet_robustness", _I32, [_P, _P, ctypes.c_uint64, ctypes.c_uint32, _P, _P, ctypes.c_uint32, _P]),
+    ("tcrnet_graph_stats", _I32, [_P, _P, ctypes.c_uint64, ctypes.c_uint32, _P, _P, _P, ctypes.c_uint32, _P,
+                                  ctypes.POINTER(tcrnet_stats)]),
+]
+_SIGS += _LATE
+if _lib is not None:  # bound already: add the late signatures
+    for _name, _res, _args in _LATE:
+        getattr(_lib, _name).restype = _res
+        getattr(_lib, _name).argtypes = _args
+
+
+def _pairs_host(pairs):
+    p = np.ascontiguousarray(np.asarray(pairs, dtype=np.uint32).reshape(-1, 2))
+    return p, len(p)
+
+
+def tcrnet_components(ctx: Context, pairs, n: int):
+    """(labels, sizes, n_components, lcc_size) of the graph on n nodes."""
+    p, E = _pairs_host(pairs)
+    labels = np.zeros(max(1, n), dtype=np.uint32)
+    sizes = np.zeros(max(1, n), dtype=np.uint32)
+    info = tcrnet_cc_info()
+    _check(_lib.tcrnet_components(ctx.handle, p.ctypes.data if E else None, E, n, labels.ctypes.data,
+                                  sizes.ctypes.data, ctypes.byref(info)))
+    return labels[:n], sizes[:n], info.n_components, info.lcc_size
+
+
+def tcrnet_robustness(ctx: Context, pairs, n: int, order, removed) -> np.ndarray:
+    """LCC size after removing order[:r] for each r in removed."""
+    p, E = _pairs_host(pairs)
+    order = np.ascontiguousarray(order, dtype=np.uint32)
+    removed = np.ascontiguousarray(removed, dtype=np.uint32)
+    out = np.zeros(max(1, len(removed)), dtype=np.uint32)
+    _check(_lib.tcrnet_robustness(ctx.handle, p.ctypes.data if E else None, E, n, order.ctypes.data if n else None,
+                                  removed.ctypes.data, len(removed), out.ctypes.data))
+    return out[:len(removed)]
+
+
+def lcc_norm1(lcc, removed, n: int) -> np.ndarray:
+    """LCC(p) / ((1 - p) N) with p = removed / N (paper, "Computing LCC")."""
+    lcc = np.asarray(lcc, dtype=np.float64)
+    left = n - np.asarray(removed, dtype=np.float64)
+    return np.divide(lcc, left, out=np.zeros_like(lcc), where=left > 0)
+
+
+def lcc_norm2(lcc, removed, n: int) -> np.ndarray:
+    """LCC_norm,1(p) / LCC_norm,1(0); removed[0] must be 0."""
+    if np.asarray(removed)[0] != 0:
+        raise ValueError("removed[0] must be 0")
+    v = lcc_norm1(lcc, removed, n)
+    return v / v[0] if v[0] > 0 else v
+
+
+def tcrnet_graph_stats(ctx: Context, pairs, n: int, hist_len: int = 0) -> dict:
+    """Degree statistics, assortativity and clustering of a canonical edge
+    list (see include/tcrnet.h); hist_len 0 sizes the histograms to the
+    maximum degree (one retry)."""
+    p, E = _pairs_host(pairs)
+    hl = hist_len or 64
+    for _ in range(2):
+        deg = np.zeros(max(1, n), dtype=np.int32)
+        cnt = np.zeros(hl, dtype=np.uint64)
+        nbr = np.zeros(hl, dtype=np.uint64)
+        clu = np.zeros(max(1, n), dtype=np.float64)
+        st = tcrnet_stats()
+        rc = _lib.tcrnet_graph_stats(ctx.handle, p.ctypes.data if E else None, E, n, deg.ctypes.data,
+                                     cnt.ctypes.data, nbr.ctypes.data, hl, clu.ctypes.data, ctypes.byref(st))
+        if rc == TCRNET_ETRUNC and not hist_len:
+            hl = st.max_degree + 1
+            continue
+        _check(rc)
+        break
+    md = st.max_degree
+    return {"degree": deg[:n], "max_degree": md, "count": cnt[:md + 1], "nbr_sum": nbr[:md + 1],
+            "clustering": clu[:n], "assortativity": st.assortativity, "avg_clustering": st.avg_clustering,
+            "triangles": st.triangles, "sums": (st.sum_jk, st.sum_j_plus_k, st.sum_j2_plus_k2)}

@@ -19,6 +19,7 @@ struct tcrnet_graph {
   uint32_t n = 0;
   std::vector<uint32_t> pairs;
   std::vector<int32_t> deg;
+  std::vector<uint8_t> dist;  // weighted builds only
   tcrnet_build_info info{};
 };
 
@@ -71,7 +72,7 @@ Sched pick_sched(const tcrnet_ctx* ctx, uint64_t n, int k) {
 // capacity `cap`, re-running with the exact capacity once if the edge buffer
 // overflowed (when grow_ok).  Returns E in *E.
 int32_t run_pipeline(tcrnet_ctx* ctx, Pipeline& pl, PipeParams pp, hipStream_t st, bool grow_ok,
-                     DevBuf* pairs_buf, uint64_t* E, tcrnet_build_info* info) {
+                     DevBuf* pairs_buf, uint64_t* E, tcrnet_build_info* info, DevBuf* dist_buf) {
   Sched sched = pick_sched(ctx, pp.n, pp.k);
   pp.sched = sched;
   tcrnet_build_info inf{};
@@ -90,6 +91,11 @@ int32_t run_pipeline(tcrnet_ctx* ctx, Pipeline& pl, PipeParams pp, hipStream_t s
       e = pairs_buf->ensure(pp.capacity * 8);
       if (e != hipSuccess) return hip_error(e, "edge buffer allocation");
       pp.d_pairs = pairs_buf->as<uint32_t>();
+    }
+    if (dist_buf) {
+      e = dist_buf->ensure(pp.capacity ? pp.capacity : 1);
+      if (e != hipSuccess) return hip_error(e, "distance buffer allocation");
+      pp.d_dist = dist_buf->as<uint8_t>();
     }
     (void)hipEventRecord(ctx->ev_b0, st);
     pipeline_enqueue(pl, pp, ctx->device, st, ctx->ev_p0, ctx->ev_p1);
@@ -179,7 +185,7 @@ const char* tcrnet_status_string(int32_t s) {
 const char* tcrnet_version(void) { return kVersion; }
 
 // ----------------------------------------------------------------- builds
-int32_t tcrnet_build(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k, tcrnet_graph** out) {
+static int32_t build_host(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k, bool weighted, tcrnet_graph** out) {
   if (!out) return set_error(TCRNET_EINVAL, "NULL output pointer");
   *out = nullptr;
   if (!ctx) return set_error(TCRNET_EINVAL, "NULL context");
@@ -213,9 +219,16 @@ int32_t tcrnet_build(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k, tcrnet
     pp.capacity = default_capacity(ctx, n);
     pp.d_deg = ctx->out_deg.as<int32_t>();
     uint64_t E = 0;
-    rc = run_pipeline(ctx, ctx->pipe, pp, ctx->stream, true, &ctx->out_pairs, &E, &g->info);
+    rc = run_pipeline(ctx, ctx->pipe, pp, ctx->stream, true, &ctx->out_pairs, &E, &g->info,
+                      weighted ? &ctx->out_dist : nullptr);
     if (rc) return rc;
     g->pairs.resize(2 * E);
+    if (weighted) {
+      g->dist.resize(E);
+      if (E && (e = hipMemcpyAsync(g->dist.data(), ctx->out_dist.p, E, hipMemcpyDeviceToHost, ctx->stream)) !=
+                   hipSuccess)
+        return hip_error(e, "result copy");
+    }
     if (E && (e = hipMemcpyAsync(g->pairs.data(), ctx->out_pairs.p, E * 8, hipMemcpyDeviceToHost,
                                  ctx->stream)) != hipSuccess)
       return hip_error(e, "result copy");
@@ -226,6 +239,26 @@ int32_t tcrnet_build(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k, tcrnet
   }
   ctx->last = g->info;
   *out = g.release();
+  return TCRNET_OK;
+}
+
+int32_t tcrnet_build(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k, tcrnet_graph** out) {
+  return build_host(ctx, seqs, k, false, out);
+}
+
+int32_t tcrnet_build_weighted(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k_max, tcrnet_graph** out) {
+  if (out) *out = nullptr;
+  if (seqs && seqs->n > (1u << 29))
+    return set_error(TCRNET_EINVAL, "weighted builds take at most 2^29 sequences");
+  return build_host(ctx, seqs, k_max, true, out);
+}
+
+int32_t tcrnet_graph_distances(const tcrnet_graph* g, const uint8_t** dist, uint64_t* n_edges) {
+  if (!g || !dist || !n_edges) return set_error(TCRNET_EINVAL, "NULL argument");
+  if (g->dist.size() != g->pairs.size() / 2)
+    return set_error(TCRNET_ESTATE, "graph was not built with distances (tcrnet_build_weighted)");
+  *dist = g->dist.empty() ? nullptr : g->dist.data();
+  *n_edges = g->dist.size();
   return TCRNET_OK;
 }
 

@@ -33,7 +33,8 @@ struct tcrnet_ctx {
   hipStream_t stream = nullptr;
   tcrnet_opts opts{};
   tcr::Pipeline pipe;
-  tcr::DevBuf in_data, in_off, in_seg, out_pairs, out_deg;
+  tcr::DevBuf in_data, in_off, in_seg, out_pairs, out_deg, out_dist;
+  tcr::DevBuf ana_ws, ana_out;  // network-analysis workspace
   hipEvent_t ev_p0 = nullptr, ev_p1 = nullptr, ev_b0 = nullptr, ev_b1 = nullptr;
   std::map<std::pair<int, int>, tcr::Sched> tuned;  // (size class, k) -> schedule
   tcrnet_build_info last{};
@@ -47,6 +48,6 @@ namespace tcr {
 
 Sched pick_sched(const tcrnet_ctx* ctx, uint64_t n, int k);
 int32_t run_pipeline(tcrnet_ctx* ctx, Pipeline& pl, PipeParams pp, hipStream_t st, bool grow_ok,
-                     DevBuf* pairs_buf, uint64_t* E, tcrnet_build_info* info);
+                     DevBuf* pairs_buf, uint64_t* E, tcrnet_build_info* info, DevBuf* dist_buf = nullptr);
 
 }  // namespace tcr

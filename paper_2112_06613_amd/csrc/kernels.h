@@ -68,6 +68,7 @@ struct PairArgs {
   const Plan* plan;
   Counters* cnt;
   uint32_t* edges;      // 2 * capacity words
+  uint8_t* edist;       // capacity bytes: distance of each edge (NULL: not kept)
   uint64_t capacity;
   uint32_t texts_per_item;
   int32_t k;
@@ -76,10 +77,11 @@ void launch_pairs(const PairArgs& a, uint32_t grid_blocks, bool peq_lds, hipStre
 uint32_t pair_grid_blocks(int device, uint32_t waves_per_simd);
 
 // Step a8: canonical keys.  mode 0: (min, max) of the ids.  mode 1: the id
-// carrying kQueryTag first (tag removed).  key = (first << shift) | second.
+// carrying kQueryTag first (tag removed).  key = (first << shift) | second,
+// followed by the 5-bit distance when edist is not NULL.
 // The edge count is min(E_max, *dE) (dE may be NULL).
-void launch_edge_keys(const uint32_t* edges, uint64_t E_max, const unsigned long long* dE, int mode, int shift,
-                      uint64_t* keys, hipStream_t st);
+void launch_edge_keys(const uint32_t* edges, const uint8_t* edist, uint64_t E_max, const unsigned long long* dE,
+                      int mode, int shift, uint64_t* keys, hipStream_t st);
 // Degrees of an insert: for each of the E pairs (i, j) add 1 to deg[i] and
 // deg[j], and to counts[x - n_old] for each end x >= n_old.
 void launch_insert_degrees(const uint32_t* pairs, const unsigned long long* dE, uint64_t E_max, uint32_t n_old,
@@ -87,7 +89,8 @@ void launch_insert_degrees(const uint32_t* pairs, const unsigned long long* dE, 
 
 // Step a7: unpack sorted keys to pairs and add both ends (mode 0) or the
 // first end (mode 1) to deg (NULL: no degrees).
+// With dist_out != NULL the keys carry a 5-bit distance (written there).
 void launch_unpack(const uint64_t* keys, uint64_t E_max, const unsigned long long* dE, int mode, int shift,
-                   uint32_t* pairs, int32_t* deg, hipStream_t st);
+                   uint32_t* pairs, int32_t* deg, uint8_t* dist_out, hipStream_t st);
 
 }  // namespace tcr

@@ -4,12 +4,15 @@
 // 1999) in the formulation of Hyyro (2001/2003), one 32-bit word per pattern.
 // Column j of the DP table (text prefix of length j) is held as vertical
 // deltas VP (+1) and VN (-1); the top row is D[0][j] = j, so the horizontal
-// delta entering row 1 is +1 at every step (the "| 1" after the shift).
+// delta entering row 1 is +1 at every step (the "+ 1" after the shift, which
+// equals "| 1" because the shifted word has bit 0 clear).
 //
 // Early exit: D never decreases along a diagonal (Ukkonen 1985), so after
 // text step j the cell D[r][j] on the final diagonal r = j + m - n is a lower
-// bound of lev = D[m][n].  It is read from the deltas:
-//   D[r][j] = j + popcount(VP & (2^r - 1)) - popcount(VN & (2^r - 1)).
+// bound of lev = D[m][n].  Hyyro's D0 word has bit r-1 set exactly when
+// D[r][j] = D[r-1][j-1] (a zero step along the diagonal), so collecting, at
+// each step, the D0 bit of the diagonal's current row into one word DG gives
+//   D[r][j] = max(m - n, 0) + j - popcount(DG).
 // The paper aborts once the smallest entry of a DP row exceeds l_max
 // ("GPU-based network generation"); the diagonal cell is the tighter exact
 // bound of the same kind.  A bound above k for every lane of a wave ends the
@@ -38,6 +41,9 @@ __device__ __forceinline__ uint64_t rfl64(uint64_t v) {
 }
 
 __device__ __forceinline__ uint32_t low_mask(uint32_t r) { return r >= 32 ? ~0u : ((1u << r) - 1u); }
+
+// (h << 1) | 1 as one funnel shift: the low 32 bits of (h:0xffffffff) >> 31.
+__device__ __forceinline__ uint32_t shl1_or1(uint32_t h) { return __builtin_amdgcn_alignbit(h, 0xffffffffu, 31); }
 
 // Loads through address-space views of descriptor pointers: the wave-uniform
 // text records are read-only for the whole launch, so they are read through
@@ -71,7 +77,8 @@ template <bool kPeqLds>
 __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs,
                                                   const uint64_t* __restrict__ item_base,
                                                   const Plan* __restrict__ plan, Counters* __restrict__ cnt,
-                                                  uint32_t* __restrict__ edges, uint64_t capacity,
+                                                  uint32_t* __restrict__ edges, uint8_t* __restrict__ edist,
+                                                  uint64_t capacity,
                                                   uint32_t T, int k) {
   __shared__ uint32_t lds_eq[kPeqLds ? (kBlock / kWave) * kAlpha * kWave : 1];
   const uint32_t lane = threadIdx.x & 63u;
@@ -120,12 +127,19 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
 
     const uint32_t m = d.m, n = d.n;
     const uint32_t Mm = low_mask(m);
+    const int delta = (int)m - (int)n;    // final diagonal: row = column + delta
+    const int dpos = delta > 0 ? delta : 0;
+    const uint32_t diag0 = delta >= 0 ? (1u << delta) : 0u;  // diagonal row of text step 1
     uint32_t tb = d.t0 + c * T;
     const uint32_t te = min(d.t0 + d.nt, tb + T);
     if (d.tri && tb < gbase + 1) tb = gbase + 1;
 
+    // the next text's record is loaded one text ahead (scalar loads overlap
+    // the current text's steps)
+    SeqRec nxt = load_const(trec, tb < te ? tb : 0u);
     for (uint32_t t = tb; t < te; ++t) {
-      const SeqRec tr = load_const(trec, t);
+      const SeqRec tr = nxt;
+      if (t + 1 < te) nxt = load_const(trec, t + 1);
       uint64_t valid = lane_mask;
       if (d.tri) {
         const uint32_t lim = t - gbase;  // lanes with pattern < text
@@ -143,29 +157,32 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     const uint32_t D0 = (((Eq & VP) + VP) ^ VP) | Eq | VN;                   \
     const uint32_t HP = VN | ~(D0 | VP);                                     \
     const uint32_t HN = D0 & VP;                                             \
-    const uint32_t X = (HP << 1) | 1u;                                       \
+    const uint32_t X = shl1_or1(HP);                                         \
     VN = X & D0;                                                             \
     VP = (HN << 1) | ~(X | D0);                                              \
-    const int r = (J) + 1 + (int)m - (int)n;                                 \
-    if (r >= 1) {                                                            \
-      const uint32_t Mr = low_mask((uint32_t)r);                             \
-      /* D[r][J+1] <= k  <=>  popc(VP&Mr) + J + 1 <= popc(VN&Mr) + k */     \
-      const uint32_t up = (uint32_t)__popc(VP & Mr) + (uint32_t)((J) + 1);   \
-      const uint32_t dn = (uint32_t)__popc(VN & Mr) + (uint32_t)k;           \
-      if ((__ballot(up <= dn) & valid) == 0ull) goto next_text;              \
+    /* the final diagonal is at row r = J + 1 + delta (bit J + delta) */     \
+    const int bit = (J) + delta;                                             \
+    if (bit >= 0) {                                                          \
+      DG |= D0 & (1u << bit);                                                \
+      /* D[r][J+1] <= k  <=>  popcount(DG) >= J + 1 + max(delta,0) - k */   \
+      const int thr = (J) + 1 + dpos - k;                                    \
+      if (thr > 0 &&                                                         \
+          (__ballot((uint32_t)__popc(DG) >= (uint32_t)thr) & valid) == 0ull) \
+        goto next_text;                                                      \
     }                                                                        \
   }
 
       // text step for character 0, from VP = 1^m, VN = 0 (then Eq & VP = Eq)
-      uint32_t VP, VN;
+      uint32_t VP, VN, DG = 0;
       {
         const uint32_t Eq = TCR_EQ(TCR_CODE(0));
         const uint32_t D0 = ((Eq + Mm) ^ Mm) | Eq;
         const uint32_t HP = ~(D0 | Mm);
         const uint32_t HN = D0 & Mm;
-        const uint32_t X = (HP << 1) | 1u;
+        const uint32_t X = shl1_or1(HP);
         VN = X & D0;
         VP = (HN << 1) | ~(X | D0);
+        DG = D0 & diag0;
       }
       TCR_STEP(1) TCR_STEP(2) TCR_STEP(3) TCR_STEP(4) TCR_STEP(5) TCR_STEP(6) TCR_STEP(7)
       TCR_STEP(8) TCR_STEP(9) TCR_STEP(10) TCR_STEP(11) TCR_STEP(12) TCR_STEP(13) TCR_STEP(14)
@@ -187,6 +204,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
             e.x = pid;
             e.y = tr.id;
             *reinterpret_cast<uint2*>(edges + 2 * slot) = e;
+            if (edist) edist[slot] = (uint8_t)dist;
           }
         }
       }
@@ -213,10 +231,10 @@ uint32_t pair_grid_blocks(int device, uint32_t waves_per_simd) {
 void launch_pairs(const PairArgs& a, uint32_t grid_blocks, bool peq_lds, hipStream_t st) {
   if (peq_lds)
     hipLaunchKernelGGL(k_pairs<true>, dim3(grid_blocks), dim3(kBlock), 0, st, a.descs, a.item_base, a.plan,
-                       a.cnt, a.edges, a.capacity, a.texts_per_item, a.k);
+                       a.cnt, a.edges, a.edist, a.capacity, a.texts_per_item, a.k);
   else
     hipLaunchKernelGGL(k_pairs<false>, dim3(grid_blocks), dim3(kBlock), 0, st, a.descs, a.item_base, a.plan,
-                       a.cnt, a.edges, a.capacity, a.texts_per_item, a.k);
+                       a.cnt, a.edges, a.edist, a.capacity, a.texts_per_item, a.k);
 }
 
 }  // namespace tcr

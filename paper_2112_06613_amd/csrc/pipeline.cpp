@@ -68,6 +68,7 @@ hipError_t pipeline_reserve(Pipeline& pl, uint64_t n, uint32_t n_seg, int k, uin
   const uint64_t tw = radix_tmp_words(nn > cap ? nn : cap);
   TCR_RESERVE(pl.tmp, tw * 4);
   TCR_RESERVE(pl.edges, cap * 8);
+  TCR_RESERVE(pl.edist, cap);
   TCR_RESERVE(pl.ekeys, cap * 8);
   TCR_RESERVE(pl.ekeys2, cap * 8);
 #undef TCR_RESERVE
@@ -118,7 +119,7 @@ void stage_prepare_records(Pipeline& pl, const SeqRec* rec, uint32_t n, const Se
 
 void stage_pairs(Pipeline& pl, const PlanPart* d_parts, uint32_t n_parts, const PlanPart& inline_part, int k,
                  const Sched& sched, uint64_t capacity, uint32_t grid_blocks, hipStream_t st, hipEvent_t ev0,
-                 hipEvent_t ev1) {
+                 hipEvent_t ev1, bool keep_dist) {
   Counters* cnt = pl.cnt();
   launch_reset_work(cnt, st);
   launch_plan(d_parts, n_parts, inline_part, k, sched.texts_per_item, pl.descs.as<Desc>(), pl.ibase.as<uint64_t>(),
@@ -129,6 +130,7 @@ void stage_pairs(Pipeline& pl, const PlanPart* d_parts, uint32_t n_parts, const 
   a.plan = pl.plan();
   a.cnt = cnt;
   a.edges = pl.edges.as<uint32_t>();
+  a.edist = keep_dist ? pl.edist.as<uint8_t>() : nullptr;
   a.capacity = capacity;
   a.texts_per_item = sched.texts_per_item;
   a.k = k;
@@ -138,13 +140,14 @@ void stage_pairs(Pipeline& pl, const PlanPart* d_parts, uint32_t n_parts, const 
 }
 
 void stage_canon(Pipeline& pl, int mode, int shift, uint64_t capacity, uint32_t* d_pairs, int32_t* d_deg,
-                 hipStream_t st) {
+                 hipStream_t st, uint8_t* d_dist) {
   Counters* cnt = pl.cnt();
-  launch_edge_keys(pl.edges.as<uint32_t>(), capacity, &cnt->edges, mode, shift, pl.ekeys.as<uint64_t>(), st);
+  launch_edge_keys(pl.edges.as<uint32_t>(), d_dist ? pl.edist.as<uint8_t>() : nullptr, capacity, &cnt->edges, mode,
+                   shift, pl.ekeys.as<uint64_t>(), st);
   const bool ealt = radix_sort(pl.ekeys.as<uint64_t>(), pl.ekeys2.as<uint64_t>(), nullptr, nullptr, capacity,
-                               &cnt->edges, 2 * shift, pl.tmp.as<uint32_t>(), st);
+                               &cnt->edges, 2 * shift + (d_dist ? 5 : 0), pl.tmp.as<uint32_t>(), st);
   const uint64_t* sk = ealt ? pl.ekeys2.as<uint64_t>() : pl.ekeys.as<uint64_t>();
-  launch_unpack(sk, capacity, &cnt->edges, mode, shift, d_pairs, d_deg, st);
+  launch_unpack(sk, capacity, &cnt->edges, mode, shift, d_pairs, d_deg, d_dist, st);
 }
 
 void pipeline_enqueue(Pipeline& pl, const PipeParams& pp, int device, hipStream_t st, hipEvent_t ev0,
@@ -163,9 +166,9 @@ void pipeline_enqueue(Pipeline& pl, const PipeParams& pp, int device, hipStream_
   part.a.n_seg = pp.n_seg;
   part.cross = 0;
   stage_pairs(pl, nullptr, 1, part, pp.k, pp.sched, pp.capacity, pair_grid_blocks(device, pp.sched.waves_per_simd),
-              st, ev0, ev1);
+              st, ev0, ev1, pp.d_dist != nullptr);
   // a7-a8
-  stage_canon(pl, 0, (int)bits_for(n), pp.capacity, pp.d_pairs, pp.d_deg, st);
+  stage_canon(pl, 0, (int)bits_for(n), pp.capacity, pp.d_pairs, pp.d_deg, st, pp.d_dist);
 }
 
 hipError_t pipeline_meta(const Pipeline& pl, Meta* host_meta, hipStream_t st) {

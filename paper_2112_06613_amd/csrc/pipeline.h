@@ -44,7 +44,7 @@ struct Sched {
 // Device buffers of one build pipeline (encode -> sort -> bucket -> plan ->
 // pairs -> canonicalise).  One per context, one per serving slot.
 struct Pipeline {
-  DevBuf rec, key, key2, val, val2, srec, speq, off, descs, ibase, meta, tmp, edges, ekeys, ekeys2;
+  DevBuf rec, key, key2, val, val2, srec, speq, off, descs, ibase, meta, tmp, edges, edist, ekeys, ekeys2;
   uint64_t n_cap = 0, e_cap = 0;
   uint32_t desc_cap = 0;
   Counters* cnt() const { return meta.as<Counters>(); }
@@ -69,6 +69,7 @@ struct PipeParams {
   uint64_t capacity = 0;               // edge capacity
   uint32_t* d_pairs = nullptr;         // 2 * capacity words (sorted output)
   int32_t* d_deg = nullptr;            // n words
+  uint8_t* d_dist = nullptr;           // capacity bytes: edge distances (NULL: not kept)
 };
 
 uint32_t bits_for(uint64_t v);  // number of bits to hold values < v (>= 1)
@@ -96,12 +97,13 @@ void stage_prepare_records(Pipeline& pl, const SeqRec* rec, uint32_t n, const Se
 // pl.edges (capacity edges).  Resets the work counters (not the input error).
 void stage_pairs(Pipeline& pl, const PlanPart* d_parts, uint32_t n_parts, const PlanPart& inline_part, int k,
                  const Sched& sched, uint64_t capacity, uint32_t grid_blocks, hipStream_t st, hipEvent_t ev0,
-                 hipEvent_t ev1);
+                 hipEvent_t ev1, bool keep_dist = false);
 
 // Stage 3 (steps a7-a8): canonical sorted pairs into d_pairs; mode 0 adds
-// both ends to deg, mode 1 (query tag first) adds the first end.
+// both ends to deg, mode 1 (query tag first) adds the first end; d_dist (may
+// be NULL) receives the distances kept by stage_pairs(keep_dist).
 void stage_canon(Pipeline& pl, int mode, int shift, uint64_t capacity, uint32_t* d_pairs, int32_t* d_deg,
-                 hipStream_t st);
+                 hipStream_t st, uint8_t* d_dist = nullptr);
 
 // Enqueue the whole build on `st` with no host synchronisation.  ev0/ev1 (may
 // be NULL) bracket the pair kernel.

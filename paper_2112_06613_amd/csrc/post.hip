@@ -11,7 +11,7 @@ __device__ __forceinline__ uint64_t eff_n(uint64_t n, const unsigned long long* 
   return v < n ? v : n;
 }
 
-__global__ void k_edge_keys(const uint32_t* __restrict__ edges, uint64_t E_max,
+__global__ void k_edge_keys(const uint32_t* __restrict__ edges, const uint8_t* __restrict__ edist, uint64_t E_max,
                             const unsigned long long* __restrict__ dE, int mode, int shift,
                             uint64_t* __restrict__ keys) {
   const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -27,15 +27,21 @@ __global__ void k_edge_keys(const uint32_t* __restrict__ edges, uint64_t E_max,
     a = (x_is_q ? p.x : p.y) & ~kQueryTag;
     b = x_is_q ? p.y : p.x;
   }
-  keys[e] = ((uint64_t)a << shift) | b;
+  uint64_t key = ((uint64_t)a << shift) | b;
+  if (edist) key = (key << 5) | edist[e];
+  keys[e] = key;
 }
 
 __global__ void k_unpack(const uint64_t* __restrict__ keys, uint64_t E_max,
                          const unsigned long long* __restrict__ dE, int mode, int shift,
-                         uint32_t* __restrict__ pairs, int32_t* __restrict__ deg) {
+                         uint32_t* __restrict__ pairs, int32_t* __restrict__ deg, uint8_t* __restrict__ dist_out) {
   const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= eff_n(E_max, dE)) return;
-  const uint64_t kv = keys[e];
+  uint64_t kv = keys[e];
+  if (dist_out) {
+    dist_out[e] = (uint8_t)(kv & 31u);
+    kv >>= 5;
+  }
   const uint32_t a = (uint32_t)(kv >> shift);
   const uint32_t b = (uint32_t)(kv & ((1ull << shift) - 1ull));
   uint2 p;
@@ -69,18 +75,18 @@ void launch_insert_degrees(const uint32_t* pairs, const unsigned long long* dE, 
                      n_old, counts, deg);
 }
 
-void launch_edge_keys(const uint32_t* edges, uint64_t E_max, const unsigned long long* dE, int mode, int shift,
-                      uint64_t* keys, hipStream_t st) {
+void launch_edge_keys(const uint32_t* edges, const uint8_t* edist, uint64_t E_max, const unsigned long long* dE,
+                      int mode, int shift, uint64_t* keys, hipStream_t st) {
   if (E_max == 0) return;
-  hipLaunchKernelGGL(k_edge_keys, dim3((uint32_t)((E_max + 255) / 256)), dim3(256), 0, st, edges, E_max, dE,
+  hipLaunchKernelGGL(k_edge_keys, dim3((uint32_t)((E_max + 255) / 256)), dim3(256), 0, st, edges, edist, E_max, dE,
                      mode, shift, keys);
 }
 
 void launch_unpack(const uint64_t* keys, uint64_t E_max, const unsigned long long* dE, int mode, int shift,
-                   uint32_t* pairs, int32_t* deg, hipStream_t st) {
+                   uint32_t* pairs, int32_t* deg, uint8_t* dist_out, hipStream_t st) {
   if (E_max == 0) return;
   hipLaunchKernelGGL(k_unpack, dim3((uint32_t)((E_max + 255) / 256)), dim3(256), 0, st, keys, E_max, dE, mode,
-                     shift, pairs, deg);
+                     shift, pairs, deg, dist_out);
 }
 
 }  // namespace tcr

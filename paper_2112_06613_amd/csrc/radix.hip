@@ -59,6 +59,63 @@ __global__ __launch_bounds__(kScanThreads) void k_radix_scan(uint32_t* __restric
   }
 }
 
+// Large scans in three passes: chunk sums, a scan of the sums, then each
+// chunk rescanned from its offset.  kScanChunk entries per block.
+constexpr int kScanChunk = 4096;
+
+__device__ uint32_t block_excl_scan_u32(uint32_t v, uint32_t* sh, uint32_t& total) {
+  const int t = threadIdx.x;
+  sh[t] = v;
+  __syncthreads();
+  for (int d = 1; d < kRB; d <<= 1) {
+    const uint32_t x = t >= d ? sh[t - d] : 0;
+    __syncthreads();
+    sh[t] += x;
+    __syncthreads();
+  }
+  total = sh[kRB - 1];
+  const uint32_t r = sh[t] - v;
+  __syncthreads();
+  return r;
+}
+
+__global__ __launch_bounds__(kRB) void k_scan_partials(const uint32_t* __restrict__ a, uint64_t total,
+                                                       uint32_t* __restrict__ partial) {
+  __shared__ uint32_t sh[kRB];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanChunk;
+  uint32_t s = 0;
+  for (int i = threadIdx.x; i < kScanChunk; i += kRB) {
+    const uint64_t idx = base + i;
+    if (idx < total) s += a[idx];
+  }
+  uint32_t tot;
+  block_excl_scan_u32(s, sh, tot);
+  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(kRB) void k_scan_chunks(uint32_t* __restrict__ a, uint64_t total,
+                                                     const uint32_t* __restrict__ partial_excl) {
+  __shared__ uint32_t sh[kRB];
+  const uint64_t base = (uint64_t)blockIdx.x * kScanChunk;
+  // each thread owns kScanChunk / kRB consecutive entries
+  constexpr int per = kScanChunk / kRB;
+  const uint64_t lo = base + (uint64_t)threadIdx.x * per;
+  uint32_t v[per];
+  uint32_t s = 0;
+#pragma unroll
+  for (int i = 0; i < per; ++i) {
+    v[i] = lo + i < total ? a[lo + i] : 0u;
+    s += v[i];
+  }
+  uint32_t tot;
+  uint32_t run = partial_excl[blockIdx.x] + block_excl_scan_u32(s, sh, tot);
+#pragma unroll
+  for (int i = 0; i < per; ++i) {
+    if (lo + i < total) a[lo + i] = run;
+    run += v[i];
+  }
+}
+
 __global__ __launch_bounds__(kRB) void k_radix_scatter(const uint64_t* __restrict__ key,
                                                        const uint32_t* __restrict__ val,
                                                        uint64_t* __restrict__ okey, uint32_t* __restrict__ oval,
@@ -116,7 +173,21 @@ __global__ __launch_bounds__(kRB) void k_radix_scatter(const uint64_t* __restric
 
 uint64_t radix_tmp_words(uint64_t n) {
   const uint64_t nb = (n + kRTile - 1) / kRTile;
-  return 256 * (nb ? nb : 1);
+  const uint64_t hist = 256 * (nb ? nb : 1);
+  return hist + (hist + kScanChunk - 1) / kScanChunk + 1;  // histogram + chunk sums
+}
+
+// Exclusive scan of `total` words in place (partial: scratch of
+// ceil(total / kScanChunk) words).
+static void scan_u32(uint32_t* a, uint64_t total, uint32_t* partial, hipStream_t st) {
+  const uint64_t chunks = (total + kScanChunk - 1) / kScanChunk;
+  if (chunks <= 8) {
+    hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(kScanThreads), 0, st, a, total);
+    return;
+  }
+  hipLaunchKernelGGL(k_scan_partials, dim3((uint32_t)chunks), dim3(kRB), 0, st, a, total, partial);
+  hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(kScanThreads), 0, st, partial, chunks);
+  hipLaunchKernelGGL(k_scan_chunks, dim3((uint32_t)chunks), dim3(kRB), 0, st, a, total, partial);
 }
 
 bool radix_sort(uint64_t* key, uint64_t* key_alt, uint32_t* val, uint32_t* val_alt, uint64_t n,
@@ -130,7 +201,7 @@ bool radix_sort(uint64_t* key, uint64_t* key_alt, uint32_t* val, uint32_t* val_a
     const uint32_t* vi = val ? (alt ? val_alt : val) : nullptr;
     uint32_t* vo = val ? (alt ? val : val_alt) : nullptr;
     hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kRB), 0, st, ki, n, d_n, shift, tmp, nb);
-    hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(kScanThreads), 0, st, tmp, (uint64_t)256 * nb);
+    scan_u32(tmp, (uint64_t)256 * nb, tmp + (uint64_t)256 * nb, st);
     hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kRB), 0, st, ki, vi, ko, vo, n, d_n, shift, tmp, nb);
     alt = !alt;
   }

@@ -46,6 +46,7 @@ constexpr uint32_t kDegHeadroom = 1u << 22;  // inserted nodes the degree array 
 
 struct Segment {
   uint32_t n = 0;
+  uint32_t hcount[33] = {0};  // host copy of the length histogram (sizing only)
   DevBuf srec, speq, off;  // off: 65 entries (one segment)
   hipEvent_t ready = nullptr;
   Segment() { (void)hipEventCreateWithFlags(&ready, hipEventDisableTiming); }
@@ -75,6 +76,7 @@ struct Request {
   std::vector<char> data;
   std::vector<uint64_t> off;  // rebased to 0
   uint32_t m = 0;
+  uint32_t hcount[33] = {0};  // length histogram of the batch (sizing only)
   int k = 1;
   bool insert = false;
   Clock::time_point t_submit;
@@ -123,6 +125,7 @@ struct Slot {
   hipEvent_t ev_meta = nullptr, ev_done = nullptr, ev_t0 = nullptr, ev_t1 = nullptr;
   Request* req = nullptr;
   int phase = 0;  // 0 idle, 1 waiting for counters, 2 waiting for results
+  uint32_t grid = 0;
   uint64_t capacity = 0;
   uint32_t n_parts = 0;
   int attempts = 0;
@@ -190,6 +193,25 @@ uint64_t request_bytes(uint32_t m, uint64_t capacity, uint32_t n_parts) {
          (uint64_t)n_parts * 160 * sizeof(Desc) + (1u << 16);
 }
 
+// Work items of a request against its snapshot, estimated from length
+// histograms (sizes the persistent grid; the plan on the device is exact).
+uint64_t estimate_items(const Request* r, uint32_t T) {
+  uint64_t items = 0;
+  auto rect = [&](uint64_t a, uint64_t b) {
+    if (a && b) items += ((a + 63) / 64) * ((b + T - 1) / T);
+  };
+  for (const SegPtr& seg : r->snap)
+    for (int L = 1; L <= 32; ++L)
+      for (int d = -r->k; d <= r->k; ++d) {
+        const int L2 = L + d;
+        if (L2 >= 1 && L2 <= 32) rect(r->hcount[L], seg->hcount[L2]);
+      }
+  if (r->insert)
+    for (int L = 1; L <= 32; ++L)
+      for (int d = 0; d <= r->k && L + d <= 32; ++d) rect(r->hcount[L + d], r->hcount[L]);
+  return items;
+}
+
 // Completion of r (held by slot s, or never admitted when s is NULL).
 void finish(tcrnet_index* idx, Slot* s, Request* r) {
   r->snap.clear();
@@ -222,7 +244,7 @@ hipError_t enqueue_pairs(tcrnet_index* idx, Slot* s) {
   if ((e = s->d_pairs.ensure(s->capacity * 8)) != hipSuccess) return e;
   if ((e = s->d_counts.ensure((uint64_t)(r->m ? r->m : 1) * 4)) != hipSuccess) return e;
   if ((e = s->h_meta.ensure(sizeof(Meta))) != hipSuccess) return e;
-  stage_pairs(s->pl, s->d_parts.as<PlanPart>(), s->n_parts, PlanPart{}, r->k, idx->sched, s->capacity, idx->grid,
+  stage_pairs(s->pl, s->d_parts.as<PlanPart>(), s->n_parts, PlanPart{}, r->k, idx->sched, s->capacity, s->grid,
               s->st, nullptr, nullptr);
   launch_fill_u32(s->d_counts.as<uint32_t>(), r->m, 0u, s->st);
   const uint32_t ids = r->n_snap + (r->insert ? r->m : 0);
@@ -249,6 +271,12 @@ hipError_t admit(tcrnet_index* idx, Slot* s, Request* r) {
   s->req = r;
   s->attempts = 0;
   s->capacity = std::max<uint64_t>(4096, (uint64_t)r->m * 16);
+  {
+    // one item per wave (4 per block) in the first round; never more than
+    // the full persistent grid
+    const uint64_t want = (estimate_items(r, idx->sched.texts_per_item) + 3) / 4;
+    s->grid = (uint32_t)std::min<uint64_t>(idx->grid, std::max<uint64_t>(16, want));
+  }
   hipStream_t st = s->st;
   (void)hipEventRecord(s->ev_t0, st);
   const uint32_t n_parts_max = (uint32_t)r->snap.size() + 1;
@@ -281,6 +309,7 @@ hipError_t admit(tcrnet_index* idx, Slot* s, Request* r) {
     stage_prepare(s->pl, s->d_data.as<char>(), s->d_off.as<uint64_t>(), r->m, nullptr, 1,
                   r->insert ? r->n_snap : 0u, r->insert ? 0u : kQueryTag, out, st);
     if (r->insert) {
+      memcpy(r->new_seg->hcount, r->hcount, sizeof r->hcount);
       (void)hipEventRecord(r->new_seg->ready, st);
       qref = r->new_seg->ref();
       idx->segs.push_back(r->new_seg);
@@ -329,6 +358,8 @@ hipError_t merge_segments(tcrnet_index* idx) {
   const uint32_t n = idx->n_total;
   auto merged = std::make_shared<Segment>();
   if ((e = merged->alloc(n)) != hipSuccess) return e;
+  for (const SegPtr& seg : idx->segs)
+    for (int L = 0; L <= 32; ++L) merged->hcount[L] += seg->hcount[L];
   if ((e = idx->merge_rec.ensure((uint64_t)(n ? n : 1) * sizeof(SeqRec))) != hipSuccess) return e;
   if ((e = pipeline_reserve(idx->merge_pl, n, 1, 1, idx->sched.texts_per_item, 1, 1)) != hipSuccess) return e;
   uint64_t pos = 0;
@@ -506,6 +537,7 @@ void copy_seqs(const tcrnet_seqs* q, Request* r) {
   }
   const uint64_t base = q->offsets[0];
   for (uint32_t i = 0; i <= q->n; ++i) r->off[i] = q->offsets[i] - base;
+  for (uint32_t i = 0; i < q->n; ++i) r->hcount[r->off[i + 1] - r->off[i]]++;  // lengths checked: 1..32
   r->data.assign(q->data + base, q->data + q->offsets[q->n]);
 }
 
@@ -532,6 +564,7 @@ int32_t tcrnet_index_create(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k_
   // base segment: the plain build at k_index gives the sorted set and degrees
   auto base = std::make_shared<Segment>();
   if ((e = base->alloc(n)) != hipSuccess) return hip_error(e, "segment allocation");
+  for (uint32_t i = 0; i < n; ++i) base->hcount[seqs->offsets[i + 1] - seqs->offsets[i]]++;
   if (n) {
     const uint64_t b0 = seqs->offsets[0], bytes = seqs->offsets[n] - b0;
     std::vector<uint64_t> off(n + 1);
@@ -566,8 +599,7 @@ int32_t tcrnet_index_create(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k_
   // serving schedule and budget
   idx->sched = pick_sched(ctx, n, k_index);
   const uint32_t n_slots = ctx->opts.max_inflight ? ctx->opts.max_inflight : 4;
-  const uint32_t full = pair_grid_blocks(ctx->device, idx->sched.waves_per_simd);
-  idx->grid = std::max<uint32_t>(64, full / n_slots);
+  idx->grid = pair_grid_blocks(ctx->device, idx->sched.waves_per_simd);  // upper bound per request
   size_t free_b = 0, total_b = 0;
   (void)hipMemGetInfo(&free_b, &total_b);
   idx->budget = ctx->opts.hbm_budget ? ctx->opts.hbm_budget : free_b / 4;

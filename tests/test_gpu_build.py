@@ -220,3 +220,29 @@ def test_device_entry_point_matches_host(tn, ctx):
     torch.cuda.synchronize()
     assert np.array_equal(exact.cpu().numpy().view(np.uint32), ref.pairs)
     assert np.array_equal(deg.cpu().numpy(), ref.degree)
+
+
+@pytest.mark.parametrize("k_max", [2, 4])
+def test_weighted_build_every_threshold(tn, ctx, orc, k_max):
+    s = synth.repertoire(3000, 300, 123)
+    g = tn.tcrnet_build_weighted(ctx, s, k_max)
+    assert g.dist is not None and len(g.dist) == len(g.pairs)
+    L = s.to_list()
+    for (i, j), d in zip(g.pairs.tolist()[::7], g.dist.tolist()[::7]):
+        assert orc.lev(L[i], L[j]) == d
+    for k in range(0, k_max + 1):
+        e, d = orc.build(s, k)
+        assert np.array_equal(g.at(k), e)
+        if k == k_max:
+            assert np.array_equal(g.degree, d)
+    plain = tn.tcrnet_build(ctx, s, k_max)
+    assert plain.dist is None and np.array_equal(plain.pairs, g.pairs)
+
+
+def test_valu_peak_probe(tn, ctx):
+    # measured 32-bit VALU issue rate of xor/add chains: above one wave64
+    # instruction per SIMD per 4 clocks at half the clock, and not above the
+    # dual-issue peak 256 CUs x 128 lanes x 2.4 GHz (margin for the timer)
+    rate, sec = tn.tcrnet_valu_peak(ctx)
+    assert sec > 0
+    assert 0.5 * 256 * 64 * 2.4e9 < rate < 1.05 * 256 * 128 * 2.4e9
