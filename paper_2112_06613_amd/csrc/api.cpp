@@ -479,8 +479,8 @@ int32_t tcrnet_autotune(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k) {
   (void)hipMemcpyAsync(ctx->in_off.p, off.data(), (n + 1) * 8, hipMemcpyHostToDevice, ctx->stream);
   const uint32_t saved_flags = ctx->opts.flags;
   const tcrnet_opts saved = ctx->opts;
-  const uint32_t Ts[] = {256, 512, 1024, 2048};
-  const uint32_t Ws[] = {4, 6, 8};
+  const uint32_t Ts[] = {1024, 4096, 16384, 65536};
+  const uint32_t Ws[] = {4, 8};
   const bool Ls[] = {false, true};
   double best = 1e30;
   Sched best_s;

@@ -11,17 +11,33 @@ constexpr int kWave = 64;        // CDNA wavefront
 constexpr int kBlock = 256;      // threads per block of the pair kernel (4 waves)
 constexpr uint32_t kQueryTag = 0x80000000u;  // id bit marking the query side
 
-// One sequence as the pair kernel reads it (32 bytes, read with one scalar
+constexpr int kSkipDepths = 8;   // prefix depths with a group-end pointer
+
+// One sequence as the pair kernel reads it (64 bytes, read with one scalar
 // load when the sequence is the wave-uniform text).
 //   w[0..5]: 5-bit residue codes, 6 per word, code q in w[q/6] bits 5*(q%6)
 //   len:     number of residues (1..32)
 //   id:      caller-visible node id (input position; in query mode the query
 //            side carries kQueryTag)
-struct alignas(32) SeqRec {
+//   nxt[d-1] (sorted records only): the first sorted position after this one
+//            whose (segment, length, first d residues) differ -- the end of
+//            this sequence's depth-d prefix group; the position + 1 when the
+//            sort key holds fewer than d residues.
+struct alignas(64) SeqRec {
+  uint32_t w[6];
+  uint32_t len;
+  uint32_t id;
+  uint32_t nxt[kSkipDepths];
+};
+
+// The first half of a SeqRec (codes, length, id): what the pair kernel reads
+// of a text up front.
+struct alignas(32) SeqHead {
   uint32_t w[6];
   uint32_t len;
   uint32_t id;
 };
+static_assert(sizeof(SeqRec) == 2 * sizeof(SeqHead), "SeqRec = head + group ends");
 
 // Bit masks of one pattern: eq[c] has bit q set iff residue q has code c
 // (Myers' Peq table).  80 bytes.

@@ -47,9 +47,11 @@ bool radix_sort(uint64_t* key, uint64_t* key_alt, uint32_t* val, uint32_t* val_a
 void launch_bucket_bounds(const uint64_t* key, uint64_t n, int combo_shift, uint32_t n_combo,
                           uint32_t* off, hipStream_t st);
 
-// Gather records into sorted order and build each pattern's bit masks.
-void launch_gather(const SeqRec* rec, const uint32_t* val, uint64_t n, SeqRec* srec, PeqRec* speq,
-                   hipStream_t st);
+// Gather records into sorted order (val: sorted position -> record; skey:
+// the sorted keys of a sort with seg_bits segment bits), fill each record's
+// prefix-group ends and build each pattern's bit masks.
+void launch_gather(const SeqRec* rec, const uint32_t* val, const uint64_t* skey, uint64_t n, uint32_t seg_bits,
+                   SeqRec* srec, PeqRec* speq, hipStream_t st);
 
 // Step a3: bucket-pair work plan over a list of parts (device array d_parts
 // of n_parts entries, or the single inline_part when d_parts is NULL).

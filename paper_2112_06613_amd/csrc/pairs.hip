@@ -42,9 +42,6 @@ __device__ __forceinline__ uint64_t rfl64(uint64_t v) {
 
 __device__ __forceinline__ uint32_t low_mask(uint32_t r) { return r >= 32 ? ~0u : ((1u << r) - 1u); }
 
-// (h << 1) | 1 as one funnel shift: the low 32 bits of (h:0xffffffff) >> 31.
-__device__ __forceinline__ uint32_t shl1_or1(uint32_t h) { return __builtin_amdgcn_alignbit(h, 0xffffffffu, 31); }
-
 // Loads through address-space views of descriptor pointers: the wave-uniform
 // text records are read-only for the whole launch, so they are read through
 // the constant address space (scalar loads into SGPRs); pattern data through
@@ -73,13 +70,28 @@ __device__ __forceinline__ T load_global(const T* p, uint32_t i) {
 #endif
 }
 
-template <bool kPeqLds>
+// 2x and 2x + 1 as integer adds (a shift by one is the same value; on gfx950
+// the adds issue at twice the rate of shifts and funnel shifts).
+__device__ __forceinline__ uint32_t twice(uint32_t x) {
+  uint32_t r;
+  asm("v_add_u32 %0, %1, %1" : "=v"(r) : "v"(x));
+  return r;
+}
+__device__ __forceinline__ uint32_t twice_plus1(uint32_t x) {
+  uint32_t r;
+  asm("v_add3_u32 %0, %1, %1, 1" : "=v"(r) : "v"(x));
+  return r;
+}
+
+// kMode: how a lane's remaining miss budget on the final diagonal is held.
+//   1, 2: as wave masks in SGPRs, A_i = lanes whose budget is >= i (k <= kMode)
+//   0:    as a per-lane counter (any k)
+template <bool kPeqLds, int kMode>
 __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs,
                                                   const uint64_t* __restrict__ item_base,
                                                   const Plan* __restrict__ plan, Counters* __restrict__ cnt,
                                                   uint32_t* __restrict__ edges, uint8_t* __restrict__ edist,
-                                                  uint64_t capacity,
-                                                  uint32_t T, int k) {
+                                                  uint64_t capacity, uint32_t T, int k) {
   __shared__ uint32_t lds_eq[kPeqLds ? (kBlock / kWave) * kAlpha * kWave : 1];
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wid = threadIdx.x >> 6;
@@ -125,92 +137,139 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     }
     const uint32_t pid = load_global(prec, p).id;
 
-    const uint32_t m = d.m, n = d.n;
+    const uint32_t m = d.m, n = d.n;  // m >= n: the pattern is the longer string
     const uint32_t Mm = low_mask(m);
-    const int delta = (int)m - (int)n;    // final diagonal: row = column + delta
-    const int dpos = delta > 0 ? delta : 0;
-    const uint32_t diag0 = delta >= 0 ? (1u << delta) : 0u;  // diagonal row of text step 1
+    const uint32_t delta = m - n;     // final diagonal: row = column + delta
+    const int budget0 = k - (int)delta;  // misses allowed on the final diagonal
     uint32_t tb = d.t0 + c * T;
     const uint32_t te = min(d.t0 + d.nt, tb + T);
     if (d.tri && tb < gbase + 1) tb = gbase + 1;
 
-    // the next text's record is loaded one text ahead (scalar loads overlap
-    // the current text's steps)
-    SeqRec nxt = load_const(trec, tb < te ? tb : 0u);
-    for (uint32_t t = tb; t < te; ++t) {
-      const SeqRec tr = nxt;
-      if (t + 1 < te) nxt = load_const(trec, t + 1);
+    const uint32_t* tnxt = reinterpret_cast<const uint32_t*>(trec) + 8;  // nxt[] of record 0
+    uint32_t t = tb;
+    while (t < te) {
+      const SeqHead tr = load_const(reinterpret_cast<const SeqHead*>(trec), 2 * t);
+      uint32_t tn = t + 1;  // next text
       uint64_t valid = lane_mask;
+      bool can_skip = true;
       if (d.tri) {
         const uint32_t lim = t - gbase;  // lanes with pattern < text
-        if (lim < 64) valid &= (1ull << lim) - 1ull;
+        if (lim < 64) {
+          valid &= (1ull << lim) - 1ull;
+          can_skip = false;  // the next texts add valid lanes
+        }
       }
+      // per-text copies the compiler cannot see through, so that the per-step
+      // length tests are formed inside the loop instead of being hoisted
+      // into (spilled) registers
+      uint32_t nn = n;
+      asm volatile("" : "+s"(nn));
+      uint32_t mJ = 1u << delta;  // D0 bit of the final diagonal at the current step
+      uint32_t ex = 32;           // text step after which no lane was within k (32: none)
 
+      uint64_t A0 = valid, A1 = 0, A2 = 0;
+      int bud = budget0;
+      if (kMode >= 1 && budget0 >= 1) A1 = valid;
+      if (kMode >= 2 && budget0 >= 2) A2 = valid;
+
+// Miss accounting for a text step with zero-step word D0: b = lanes whose
+// step along the final diagonal is zero (D0 bit of the diagonal row set);
+// every other lane spends one unit of budget.  A0 = lanes still within k.
+// The diagonal row moves down one bit per step.
+#define TCR_MISS(D0)                                                           \
+  if (kMode == 0) {                                                            \
+    bud -= ((D0) & mJ) == 0u ? 1 : 0;                                          \
+    A0 = __ballot(bud >= 0) & valid;                                           \
+  } else {                                                                     \
+    const uint64_t b = __ballot(((D0) & mJ) != 0u);                            \
+    if (kMode >= 2) {                                                          \
+      A0 = (A0 & b) | A1;                                                      \
+      A1 = (A1 & b) | A2;                                                      \
+      A2 &= b;                                                                 \
+    } else {                                                                   \
+      A0 = (A0 & b) | A1;                                                      \
+      A1 &= b;                                                                 \
+    }                                                                          \
+  }                                                                            \
+  mJ = twice(mJ);
 #define TCR_EQ(cc) (kPeqLds ? wave_eq[(cc) * kWave + lane] : eq[(cc)])
 #define TCR_CODE(q) ((tr.w[(q) / 6] >> (5 * ((q) % 6))) & 31u)
-// One text step for character J (0-based, J >= 1), then the exit test on the
-// final diagonal once it has entered the table (r >= 1).
-#define TCR_STEP(J)                                                          \
-  {                                                                          \
-    if ((uint32_t)(J) >= n) goto final_check;                                \
-    const uint32_t Eq = TCR_EQ(TCR_CODE(J));                                 \
-    const uint32_t D0 = (((Eq & VP) + VP) ^ VP) | Eq | VN;                   \
-    const uint32_t HP = VN | ~(D0 | VP);                                     \
-    const uint32_t HN = D0 & VP;                                             \
-    const uint32_t X = shl1_or1(HP);                                         \
-    VN = X & D0;                                                             \
-    VP = (HN << 1) | ~(X | D0);                                              \
-    /* the final diagonal is at row r = J + 1 + delta (bit J + delta) */     \
-    const int bit = (J) + delta;                                             \
-    if (bit >= 0) {                                                          \
-      DG |= D0 & (1u << bit);                                                \
-      /* D[r][J+1] <= k  <=>  popcount(DG) >= J + 1 + max(delta,0) - k */   \
-      const int thr = (J) + 1 + dpos - k;                                    \
-      if (thr > 0 &&                                                         \
-          (__ballot((uint32_t)__popc(DG) >= (uint32_t)thr) & valid) == 0ull) \
-        goto next_text;                                                      \
-    }                                                                        \
+// Text steps are nested ifs (structured control flow, so every exit stays a
+// plain scalar branch): step J runs only while J < n and some lane is still
+// within k; a wave with none left records the step in ex.
+#define TCR_OPEN(J)                                                            \
+  if ((uint32_t)(J) < nn) {                                                    \
+    const uint32_t Eq = TCR_EQ(TCR_CODE(J));                                   \
+    const uint32_t D0 = (((Eq & VP) + VP) ^ VP) | Eq | VN;                     \
+    const uint32_t HP = VN | ~(D0 | VP);                                       \
+    const uint32_t HN = D0 & VP;                                               \
+    const uint32_t X = twice_plus1(HP);                                        \
+    VN = X & D0;                                                               \
+    VP = twice(HN) | ~(X | D0);                                                \
+    TCR_MISS(D0)                                                               \
+    if (A0 != 0ull) {
+#define TCR_CLOSE(J)                                                           \
+    } else {                                                                   \
+      ex = (J);                                                                \
+    }                                                                          \
   }
 
       // text step for character 0, from VP = 1^m, VN = 0 (then Eq & VP = Eq)
-      uint32_t VP, VN, DG = 0;
+      uint32_t VP, VN;
       {
         const uint32_t Eq = TCR_EQ(TCR_CODE(0));
         const uint32_t D0 = ((Eq + Mm) ^ Mm) | Eq;
         const uint32_t HP = ~(D0 | Mm);
         const uint32_t HN = D0 & Mm;
-        const uint32_t X = shl1_or1(HP);
+        const uint32_t X = twice_plus1(HP);
         VN = X & D0;
-        VP = (HN << 1) | ~(X | D0);
-        DG = D0 & diag0;
+        VP = twice(HN) | ~(X | D0);
+        TCR_MISS(D0)
       }
-      TCR_STEP(1) TCR_STEP(2) TCR_STEP(3) TCR_STEP(4) TCR_STEP(5) TCR_STEP(6) TCR_STEP(7)
-      TCR_STEP(8) TCR_STEP(9) TCR_STEP(10) TCR_STEP(11) TCR_STEP(12) TCR_STEP(13) TCR_STEP(14)
-      TCR_STEP(15) TCR_STEP(16) TCR_STEP(17) TCR_STEP(18) TCR_STEP(19) TCR_STEP(20) TCR_STEP(21)
-      TCR_STEP(22) TCR_STEP(23) TCR_STEP(24) TCR_STEP(25) TCR_STEP(26) TCR_STEP(27) TCR_STEP(28)
-      TCR_STEP(29) TCR_STEP(30) TCR_STEP(31)
-    final_check : {
-      const int dist = (int)n + __popc(VP & Mm) - __popc(VN & Mm);
-      const bool hit = ((valid >> lane) & 1ull) && dist <= k;
-      const uint64_t hm = __ballot(hit);
-      if (hm) {
-        unsigned long long base = 0;
-        if (lane == 0) base = atomicAdd(&cnt->edges, (unsigned long long)__popcll(hm));
-        base = rfl64(base);
-        if (hit) {
-          const uint64_t slot = base + (uint64_t)__popcll(hm & lt_mask);
-          if (slot < capacity) {
-            uint2 e;
-            e.x = pid;
-            e.y = tr.id;
-            *reinterpret_cast<uint2*>(edges + 2 * slot) = e;
-            if (edist) edist[slot] = (uint8_t)dist;
+      if (A0 != 0ull) {
+        TCR_OPEN(1) TCR_OPEN(2) TCR_OPEN(3) TCR_OPEN(4) TCR_OPEN(5) TCR_OPEN(6) TCR_OPEN(7) TCR_OPEN(8)
+        TCR_OPEN(9) TCR_OPEN(10) TCR_OPEN(11) TCR_OPEN(12) TCR_OPEN(13) TCR_OPEN(14) TCR_OPEN(15)
+        TCR_OPEN(16) TCR_OPEN(17) TCR_OPEN(18) TCR_OPEN(19) TCR_OPEN(20) TCR_OPEN(21) TCR_OPEN(22)
+        TCR_OPEN(23) TCR_OPEN(24) TCR_OPEN(25) TCR_OPEN(26) TCR_OPEN(27) TCR_OPEN(28) TCR_OPEN(29)
+        TCR_OPEN(30) TCR_OPEN(31)
+        TCR_CLOSE(31) TCR_CLOSE(30) TCR_CLOSE(29) TCR_CLOSE(28) TCR_CLOSE(27) TCR_CLOSE(26)
+        TCR_CLOSE(25) TCR_CLOSE(24) TCR_CLOSE(23) TCR_CLOSE(22) TCR_CLOSE(21) TCR_CLOSE(20)
+        TCR_CLOSE(19) TCR_CLOSE(18) TCR_CLOSE(17) TCR_CLOSE(16) TCR_CLOSE(15) TCR_CLOSE(14)
+        TCR_CLOSE(13) TCR_CLOSE(12) TCR_CLOSE(11) TCR_CLOSE(10) TCR_CLOSE(9) TCR_CLOSE(8)
+        TCR_CLOSE(7) TCR_CLOSE(6) TCR_CLOSE(5) TCR_CLOSE(4) TCR_CLOSE(3) TCR_CLOSE(2) TCR_CLOSE(1)
+      } else {
+        ex = 0;
+      }
+
+      if (ex < 32) {
+        // every text sharing this text's first ex+1 residues ends at the same
+        // step with no lane within k: jump past that prefix group (possible
+        // while the set of valid lanes cannot grow)
+        if (ex < (uint32_t)kSkipDepths && can_skip) tn = max(load_const(tnxt, 16 * t + ex), t + 1);
+      } else {
+        // A0: valid lanes whose final distance D[m][n] = delta + misses <= k
+        const uint64_t hm = A0;
+        if (hm) {
+          const bool hit = (hm >> lane) & 1ull;
+          unsigned long long base = 0;
+          if (lane == 0) base = atomicAdd(&cnt->edges, (unsigned long long)__popcll(hm));
+          base = rfl64(base);
+          if (hit) {
+            const uint64_t slot = base + (uint64_t)__popcll(hm & lt_mask);
+            if (slot < capacity) {
+              uint2 e;
+              e.x = pid;
+              e.y = tr.id;
+              *reinterpret_cast<uint2*>(edges + 2 * slot) = e;
+              if (edist) edist[slot] = (uint8_t)((int)n + __popc(VP & Mm) - __popc(VN & Mm));
+            }
           }
         }
       }
-    }
-    next_text:;
-#undef TCR_STEP
+      t = tn;
+#undef TCR_OPEN
+#undef TCR_CLOSE
+#undef TCR_MISS
 #undef TCR_EQ
 #undef TCR_CODE
     }
@@ -222,19 +281,27 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
 
 uint32_t pair_grid_blocks(int device, uint32_t waves_per_simd) {
   int cus = 256;
-  hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
+  (void)hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device);
   if (waves_per_simd == 0) waves_per_simd = 8;
   // a block is 4 waves, one per SIMD of a CU
   return (uint32_t)cus * waves_per_simd;
 }
 
 void launch_pairs(const PairArgs& a, uint32_t grid_blocks, bool peq_lds, hipStream_t st) {
-  if (peq_lds)
-    hipLaunchKernelGGL(k_pairs<true>, dim3(grid_blocks), dim3(kBlock), 0, st, a.descs, a.item_base, a.plan,
-                       a.cnt, a.edges, a.edist, a.capacity, a.texts_per_item, a.k);
-  else
-    hipLaunchKernelGGL(k_pairs<false>, dim3(grid_blocks), dim3(kBlock), 0, st, a.descs, a.item_base, a.plan,
-                       a.cnt, a.edges, a.edist, a.capacity, a.texts_per_item, a.k);
+#define TCR_LAUNCH(LDS, MODE)                                                                              \
+  hipLaunchKernelGGL((k_pairs<LDS, MODE>), dim3(grid_blocks), dim3(kBlock), 0, st, a.descs, a.item_base, a.plan, \
+                     a.cnt, a.edges, a.edist, a.capacity, a.texts_per_item, a.k)
+  const int mode = a.k <= 1 ? 1 : (a.k == 2 ? 2 : 0);
+  if (peq_lds) {
+    if (mode == 1) TCR_LAUNCH(true, 1);
+    else if (mode == 2) TCR_LAUNCH(true, 2);
+    else TCR_LAUNCH(true, 0);
+  } else {
+    if (mode == 1) TCR_LAUNCH(false, 1);
+    else if (mode == 2) TCR_LAUNCH(false, 2);
+    else TCR_LAUNCH(false, 0);
+  }
+#undef TCR_LAUNCH
 }
 
 }  // namespace tcr

@@ -97,7 +97,7 @@ void stage_prepare(Pipeline& pl, const char* d_data, const uint64_t* d_off, uint
   const uint64_t* skey = alt ? pl.key2.as<uint64_t>() : pl.key.as<uint64_t>();
   const uint32_t* sval = alt ? pl.val2.as<uint32_t>() : pl.val.as<uint32_t>();
   launch_bucket_bounds(skey, n, encode_combo_shift(seg_bits), n_combo, off, st);
-  launch_gather(pl.rec.as<SeqRec>(), sval, n, srec, speq, st);
+  launch_gather(pl.rec.as<SeqRec>(), sval, skey, n, seg_bits, srec, speq, st);
 }
 
 void stage_prepare_records(Pipeline& pl, const SeqRec* rec, uint32_t n, const SetOut& out, hipStream_t st) {
@@ -114,7 +114,7 @@ void stage_prepare_records(Pipeline& pl, const SeqRec* rec, uint32_t n, const Se
   const uint64_t* skey = alt ? pl.key2.as<uint64_t>() : pl.key.as<uint64_t>();
   const uint32_t* sval = alt ? pl.val2.as<uint32_t>() : pl.val.as<uint32_t>();
   launch_bucket_bounds(skey, n, encode_combo_shift(0), 64, off, st);
-  launch_gather(rec, sval, n, srec, speq, st);
+  launch_gather(rec, sval, skey, n, 0, srec, speq, st);
 }
 
 void stage_pairs(Pipeline& pl, const PlanPart* d_parts, uint32_t n_parts, const PlanPart& inline_part, int k,

@@ -100,6 +100,8 @@ __global__ void k_encode(const char* __restrict__ data, const uint64_t* __restri
   for (int q = 0; q < 6; ++q) r.w[q] = w[q];
   r.len = len;
   r.id = (id_base + i) | id_tag;
+#pragma unroll
+  for (int q = 0; q < kSkipDepths; ++q) r.nxt[q] = 0;
   rec[i] = r;
   key[i] = ((uint64_t)seg << seg_shift) | ((uint64_t)len << len_shift) | lex;
   val[i] = i;
@@ -115,11 +117,41 @@ __global__ void k_bounds(const uint64_t* __restrict__ key, uint64_t n, int shift
   for (uint32_t c = first; c <= cur && c <= n_combo; ++c) off[c] = (uint32_t)s;
 }
 
-__global__ void k_gather(const SeqRec* __restrict__ rec, const uint32_t* __restrict__ val, uint64_t n,
-                         SeqRec* __restrict__ srec, PeqRec* __restrict__ speq) {
+// Sorted record s with its prefix-group ends (deepest first: the group at
+// depth d contains the one at depth d + 1, so each search starts from the last
+// known member, galloping then bisecting over the sorted keys).
+__global__ void k_gather(const SeqRec* __restrict__ rec, const uint32_t* __restrict__ val,
+                         const uint64_t* __restrict__ skey, uint64_t n, int nres, SeqRec* __restrict__ srec,
+                         PeqRec* __restrict__ speq) {
   const uint64_t s = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= n) return;
-  const SeqRec r = rec[val[s]];
+  SeqRec r = rec[val[s]];
+  const uint64_t key = skey[s];
+  uint64_t lo = s;  // last position known to share the current prefix
+  for (int d = kSkipDepths; d >= 1; --d) {
+    if (d > nres) {
+      r.nxt[d - 1] = (uint32_t)(s + 1);
+      continue;
+    }
+    const int sh = 5 * (nres - d);
+    const uint64_t pre = key >> sh;
+    uint64_t hi = n, step = 1;
+    for (;;) {
+      const uint64_t p = lo + step;
+      if (p >= n) break;
+      if ((skey[p] >> sh) != pre) {
+        hi = p;
+        break;
+      }
+      lo = p;
+      step <<= 1;
+    }
+    while (hi - lo > 1) {
+      const uint64_t mid = (lo + hi) >> 1;
+      if ((skey[mid] >> sh) == pre) lo = mid; else hi = mid;
+    }
+    r.nxt[d - 1] = (uint32_t)hi;
+  }
   srec[s] = r;
   // bit planes of the residue codes, then Peq[c] = positions whose code is c
   uint32_t pl[5] = {0, 0, 0, 0, 0};
@@ -364,10 +396,11 @@ void launch_bucket_bounds(const uint64_t* key, uint64_t n, int combo_shift, uint
                      off);
 }
 
-void launch_gather(const SeqRec* rec, const uint32_t* val, uint64_t n, SeqRec* srec, PeqRec* speq,
-                   hipStream_t st) {
+void launch_gather(const SeqRec* rec, const uint32_t* val, const uint64_t* skey, uint64_t n, uint32_t seg_bits,
+                   SeqRec* srec, PeqRec* speq, hipStream_t st) {
   if (n == 0) return;
-  hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, 256)), dim3(256), 0, st, rec, val, n, srec, speq);
+  hipLaunchKernelGGL(k_gather, dim3(blocks_for(n, 256)), dim3(256), 0, st, rec, val, skey, n,
+                     encode_nres(seg_bits), srec, speq);
 }
 
 uint32_t plan_max_desc_self(uint32_t n_seg, int k, uint32_t T, uint64_t n) {
