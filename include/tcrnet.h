@@ -78,7 +78,8 @@ typedef struct {
 /* Options; a zero field selects the default.  Pass NULL for all defaults. */
 typedef struct {
   uint32_t texts_per_item;  /* texts per work item of the pair kernel
-                               (0: autotuned table / 16384) */
+                               (0: autotuned table / 16384 for builds,
+                               1024 for a serving index) */
   uint32_t waves_per_simd;  /* resident waves per SIMD of the persistent
                                pair kernel (0: 8) */
   uint64_t edge_capacity;   /* initial edge buffer capacity in edges (0: sized

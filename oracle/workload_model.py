@@ -8,8 +8,14 @@ For each workload it records
   * mean_exit_steps: the mean, over a seeded uniform sample of those pairs,
     of the text steps the exact final-diagonal early exit needs (rows = the
     longer string; computed from the oracle's full DP table, see
-    oracle_exit_step), with its standard error.
-The benchmark prices a build as evaluated_pairs * mean_exit_steps * T_step.
+    oracle_exit_step), with its standard error -- the per-pair work;
+  * wave_steps: the text steps of the pair kernel's traversal, where a wave
+    of 64 patterns walks the lexicographically sorted texts of a work item
+    and jumps past every prefix group on which all its lanes ended early
+    (replayed by workmodel.c from the oracle's exit steps over a seeded
+    uniform sample of work items, or all items when few), with the number of
+    visited texts and the standard error.
+The benchmark prices a build as wave_steps * 64 lanes * T_step.
 
 Usage: python -m oracle.workload_model [--samples 400000]
 """
@@ -73,7 +79,120 @@ def sample_pairs(lengths: np.ndarray, k: int, n_samples: int, seed: int):
     return pi, pj, int(w.sum())
 
 
-def model(seqs, k: int, n_samples: int, seed: int = 1) -> dict:
+ALPHABET = "ARNDCQEGHILKMFPSTWYV"
+SORT_RESIDUES = 11   # residues in the sort key of a one-segment build
+DEPTHS = 8           # prefix depths with a group end
+WAVE = 64
+
+
+def code_matrix(seqs):
+    """n x 32 residue codes (0 past the end) and the lengths."""
+    lut = np.zeros(256, dtype=np.uint8)
+    for i, c in enumerate(ALPHABET):
+        lut[ord(c)] = i
+    L = seqs.lengths().astype(np.int64)
+    n = seqs.n
+    M = np.zeros((n, 32), dtype=np.uint8)
+    row = np.repeat(np.arange(n), L)
+    col = np.arange(len(seqs.chars)) - np.repeat(seqs.offsets[:-1].astype(np.int64), L)
+    M[row, col] = lut[seqs.chars]
+    return M, L
+
+
+def sorted_order(M, L):
+    """Sorted position -> input id: by length, the first SORT_RESIDUES codes,
+    then input position."""
+    keys = [np.arange(len(L))] + [M[:, q] for q in reversed(range(SORT_RESIDUES))] + [L]
+    return np.lexsort(keys).astype(np.uint32)
+
+
+def group_ends(M, L, order):
+    """gend[s, d-1]: first sorted position after s whose length or first d
+    residues differ (n when none)."""
+    n = len(order)
+    Ms, Ls = M[order], L[order]
+    gend = np.empty((n, DEPTHS), dtype=np.uint32)
+    same = Ls[1:] == Ls[:-1]
+    for d in range(1, DEPTHS + 1):
+        same = same & (Ms[1:, d - 1] == Ms[:-1, d - 1])
+        start = np.ones(n, dtype=bool)
+        start[1:] = ~same
+        starts = np.flatnonzero(start)
+        gid = np.cumsum(start) - 1
+        ends = np.append(starts[1:], n).astype(np.uint32)
+        gend[:, d - 1] = ends[gid]
+    return gend
+
+
+def plan_items(L_sorted, k: int, T: int) -> np.ndarray:
+    """The pair kernel's work items of a one-segment build: rows (gbase, np,
+    tb, te, tri) over sorted positions."""
+    cnt = np.bincount(L_sorted, minlength=34)
+    off = np.concatenate([[0], np.cumsum(cnt)])
+    rows = []
+    for m in range(1, 33):
+        for delta in range(0, k + 1):
+            nl = m - delta
+            if nl < 1:
+                continue
+            npat, ntxt = int(cnt[m]), int(cnt[nl])
+            if delta > 0:
+                if npat == 0 or ntxt == 0:
+                    continue
+                g = np.arange((npat + WAVE - 1) // WAVE)
+                c = np.arange((ntxt + T - 1) // T)
+                G, C = np.meshgrid(g, c, indexing="ij")
+                gb = off[m] + WAVE * G
+                tb = off[nl] + T * C
+                te = np.minimum(off[nl] + ntxt, tb + T)
+                npg = np.minimum(WAVE, npat - WAVE * G)
+                rows.append(np.stack([gb, npg, tb, te, np.zeros_like(gb)], -1).reshape(-1, 5))
+            else:
+                if npat < 2:
+                    continue
+                for bk in range((npat - 1 + T - 1) // T):
+                    nrow = min(T, npat - bk * T)
+                    p0 = off[m] + bk * T
+                    ntb = npat - bk * T
+                    g = np.arange((nrow + WAVE - 1) // WAVE)
+                    c = np.arange((ntb + T - 1) // T)
+                    G, C = np.meshgrid(g, c, indexing="ij")
+                    gb = p0 + WAVE * G
+                    tb = p0 + T * C
+                    te = np.minimum(p0 + ntb, tb + T)
+                    tb = np.maximum(tb, gb + 1)
+                    npg = np.minimum(WAVE, nrow - WAVE * G)
+                    rows.append(np.stack([gb, npg, tb, te, np.ones_like(gb)], -1).reshape(-1, 5))
+    if not rows:
+        return np.zeros((0, 5), dtype=np.uint32)
+    return np.concatenate(rows).astype(np.uint32)
+
+
+def traversal(seqs, k: int, T: int, max_items: int, seed: int = 1) -> dict:
+    """Text steps and visited texts of the traversal over all work items
+    (exact when the items number at most max_items, else estimated from a
+    seeded uniform sample of max_items items)."""
+    M, L = code_matrix(seqs)
+    order = sorted_order(M, L)
+    gend = group_ends(M, L, order)
+    items = plan_items(L[order], k, T)
+    total = len(items)
+    exact = total <= max_items
+    if exact:
+        pick = items
+    else:
+        pick = items[np.random.default_rng(seed).choice(total, size=max_items, replace=False)]
+    steps, texts = oracle.Oracle().work_items(seqs, order, gend, pick, k)
+    steps = steps.astype(np.float64)
+    texts = texts.astype(np.float64)
+    scale = total / max(1, len(pick))
+    out = {"texts_per_item": T, "items": total, "items_modelled": int(len(pick)), "exact": bool(exact),
+           "wave_steps": float(steps.sum() * scale), "visited_texts": float(texts.sum() * scale)}
+    out["stderr_wave_steps"] = 0.0 if exact else float(steps.std(ddof=1) * total / np.sqrt(len(pick)))
+    return out
+
+
+def model(seqs, k: int, n_samples: int, seed: int = 1, T: int = 16384, max_items: int = 1 << 20) -> dict:
     lengths = seqs.lengths()
     pi, pj, evaluated = sample_pairs(lengths, k, n_samples, seed)
     steps = oracle.Oracle().exit_steps(seqs, pi, pj, k).astype(np.float64)
@@ -87,6 +206,7 @@ def model(seqs, k: int, n_samples: int, seed: int = 1) -> dict:
         "stderr_exit_steps": float(steps.std(ddof=1) / np.sqrt(len(steps))),
         "samples": n_samples,
         "sample_seed": seed,
+        "traversal": traversal(seqs, k, T, max_items, seed),
     }
 
 
@@ -94,7 +214,8 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--samples", type=int, default=400000)
     args = ap.parse_args()
-    out = {"note": "written by oracle/workload_model.py; exit steps from the oracle's full DP table",
+    out = {"note": "written by oracle/workload_model.py; exit steps from the oracle's full DP table; "
+                   "traversal = text steps of the sorted-text walk with prefix-group jumps",
            "workloads": {}}
     for name, (gen, k) in WORKLOADS.items():
         out["workloads"][name] = model(gen(), k, args.samples)

@@ -1,0 +1,67 @@
+/*
+ * Work model of the pair kernel's traversal -- BENCHMARK INFRASTRUCTURE ONLY
+ * (used by oracle/workload_model.py to price a launch; no code is shared with
+ * the HIP library).
+ *
+ * A work item is a group of up to 64 patterns and a run of texts of one
+ * length bucket, the texts in sorted order (length, residues).  For each
+ * visited text the wave needs as many text steps as its last lane needs
+ * before the final-diagonal bound exceeds k (oracle_exit_step), or all n
+ * steps when some lane ends within k.  When every lane ended early after e
+ * residues, all texts sharing those first e residues end the same way, so
+ * the walk continues at the end of that prefix group (group ends for
+ * e = 1..8, given by the caller); in a triangle item this holds only once all
+ * 64 lanes are valid (pattern before text).
+ */
+#include <stdint.h>
+
+int oracle_lev(const uint8_t* a, int m, const uint8_t* b, int n);
+int oracle_exit_step(const uint8_t* a, int m, const uint8_t* b, int n, int k);
+
+#define WM_DEPTHS 8
+
+/* One item: patterns at sorted positions [gbase, gbase + np), texts [tb, te),
+ * tri: only pairs with pattern position < text position.  seq[s] = input id
+ * of sorted position s; gend[s * 8 + d - 1] = end of s's depth-d prefix
+ * group.  Returns the text steps; *texts = texts visited. */
+static uint64_t wm_item(const uint8_t* chars, const uint64_t* offsets, const uint32_t* seq, const uint32_t* gend,
+                        uint32_t gbase, uint32_t np, uint32_t tb, uint32_t te, int tri, int k, uint64_t* texts) {
+  uint64_t steps = 0, visited = 0;
+  uint32_t t = tb;
+  while (t < te) {
+    const uint32_t b = seq[t];
+    const uint8_t* tb_ = chars + offsets[b];
+    const int n = (int)(offsets[b + 1] - offsets[b]);
+    int e = 0, full = 0;
+    for (uint32_t p = gbase; p < gbase + np; ++p) {
+      if (tri && p >= t) continue;
+      const uint32_t a = seq[p];
+      const uint8_t* pa = chars + offsets[a];
+      const int m = (int)(offsets[a + 1] - offsets[a]);
+      const int s = oracle_exit_step(pa, m, tb_, n, k);
+      if (s == n && oracle_lev(pa, m, tb_, n) <= k) full = 1;
+      if (s > e) e = s;
+    }
+    steps += full ? (uint64_t)n : (uint64_t)e;
+    visited += 1;
+    const int can_skip = !tri || t - gbase >= 64;
+    uint32_t tn = t + 1;
+    if (!full && e >= 1 && e <= WM_DEPTHS && can_skip) {
+      tn = gend[(uint64_t)t * WM_DEPTHS + (uint64_t)(e - 1)];
+      if (tn < t + 1) tn = t + 1;
+    }
+    t = tn;
+  }
+  *texts = visited;
+  return steps;
+}
+
+/* count items, item q = (gbase, np, tb, te, tri) at items[5q..5q+4]. */
+void wm_items(const uint8_t* chars, const uint64_t* offsets, const uint32_t* seq, const uint32_t* gend,
+              const uint32_t* items, int64_t count, int k, uint64_t* steps, uint64_t* texts) {
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int64_t q = 0; q < count; ++q) {
+    const uint32_t* it = items + 5 * q;
+    steps[q] = wm_item(chars, offsets, seq, gend, it[0], it[1], it[2], it[3], (int)it[4], k, &texts[q]);
+  }
+}

@@ -1,0 +1,70 @@
+"""The benchmark's work model (oracle/workmodel.c via oracle/workload_model.py):
+the prefix-group walk it replays is exact (every text a jump skips has no
+lane within k, checked against full DP distances), and the C replay matches
+a plain Python walk over the same items."""
+import numpy as np
+import pytest
+
+import oracle
+import oracle.workload_model as wm
+import synth
+
+
+def _setup(n, T, k, seed):
+    s = synth.repertoire(n, max(1, n // 10), seed)
+    M, L = wm.code_matrix(s)
+    order = wm.sorted_order(M, L)
+    gend = wm.group_ends(M, L, order)
+    items = wm.plan_items(L[order], k, T)
+    return s, L, order, gend, items
+
+
+def test_sorted_order_and_group_ends():
+    s, L, order, gend, _ = _setup(600, 64, 1, 5)
+    strs = s.to_list()
+    srt = [strs[i] for i in order]
+    assert [len(x) for x in srt] == sorted(len(x) for x in srt)
+    for p in range(len(srt)):
+        for d in range(1, wm.DEPTHS + 1):
+            e = gend[p, d - 1]
+            assert e > p
+            key = (len(srt[p]), srt[p][:d])
+            assert all((len(srt[q]), srt[q][:d]) == key for q in range(p, e))
+            assert e == len(srt) or (len(srt[e]), srt[e][:d]) != key
+
+
+@pytest.mark.parametrize("k", [1, 2])
+def test_walk_is_exact_and_matches_python(orc, k):
+    s, L, order, gend, items = _setup(500, 128, k, 9 + k)
+    strs = s.to_list()
+    steps_c, texts_c = orc.work_items(s, order, gend, items, k)
+    skipped = 0
+    for q, (gbase, npat, tb, te, tri) in enumerate(items.tolist()):
+        steps = visited = 0
+        t = tb
+        while t < te:
+            b = strs[order[t]]
+            lanes = [p for p in range(gbase, gbase + npat) if not (tri and p >= t)]
+            ex = [orc.exit_step(strs[order[p]], b, k) for p in lanes]
+            full = any(orc.lev(strs[order[p]], b) <= k for p in lanes)
+            e = max(ex)
+            steps += len(b) if full else e
+            visited += 1
+            tn = t + 1
+            if not full and e <= wm.DEPTHS and (not tri or t - gbase >= 64):
+                tn = max(int(gend[t, e - 1]), t + 1)
+                skipped += min(tn, te) - t - 1
+                # every skipped text: no lane within k (full DP distances)
+                for u in range(t + 1, min(tn, te)):
+                    bu = strs[order[u]]
+                    assert all(orc.lev(strs[order[p]], bu) > k for p in range(gbase, gbase + npat)
+                               if not (tri and p >= u))
+            t = tn
+        assert (steps, visited) == (int(steps_c[q]), int(texts_c[q]))
+    assert skipped > 0
+
+
+def test_traversal_totals_small():
+    out = wm.traversal(synth.small(), 1, 16384, 1 << 20)
+    assert out["exact"] and out["items"] == out["items_modelled"]
+    assert 0 < out["visited_texts"] <= out["wave_steps"]
