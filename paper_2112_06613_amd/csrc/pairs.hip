@@ -8,20 +8,26 @@
 // equals "| 1" because the shifted word has bit 0 clear).
 //
 // Early exit: D never decreases along a diagonal (Ukkonen 1985), so after
-// text step j the cell D[r][j] on the final diagonal r = j + m - n is a lower
-// bound of lev = D[m][n].  Hyyro's D0 word has bit r-1 set exactly when
-// D[r][j] = D[r-1][j-1] (a zero step along the diagonal), so collecting, at
-// each step, the D0 bit of the diagonal's current row into one word DG gives
-//   D[r][j] = max(m - n, 0) + j - popcount(DG).
-// The paper aborts once the smallest entry of a DP row exceeds l_max
-// ("GPU-based network generation"); the diagonal cell is the tighter exact
-// bound of the same kind.  A bound above k for every lane of a wave ends the
-// wave's work on that text; no lane's answer depends on when the check runs.
+// text step j the cell on the final diagonal, D[j+delta][j] with
+// delta = m - n >= 0, is a lower bound of lev = D[m][n].  Hyyro's D0 word has
+// bit r-1 set exactly when D[r][j] = D[r-1][j-1] (a zero step along the
+// diagonal).  Each step therefore ORs the complement of the diagonal's D0 bit
+// into a per-lane miss word Z whose bits below delta start set:
+//   popcount(Z) = D[j+delta][j]   after j steps, and = lev at the end.
+// A lane is still within k while popcount(Z) <= k.  The paper aborts once the
+// smallest entry of a DP row exceeds l_max ("GPU-based network generation");
+// the diagonal cell is the tighter exact bound of the same kind.
+//
+// Prefix-group jumps: texts are visited in sorted order.  When no lane is
+// within k after e residues of a text, the lanes' state depended only on the
+// patterns and those e residues, so every following text that shares them
+// ends the same way without an edge; the wave continues at the end of that
+// prefix group (stored in the text's record for e <= 8).
 //
 // Layout of the work: a wave holds 64 consecutive patterns of one length
 // bucket (one per lane, their Peq tables in VGPRs, or in LDS) and walks the
 // texts of a chunk of another (or the same) bucket; each text is
-// wave-uniform and is read with one scalar load into SGPRs.  Sequences are
+// wave-uniform and is read with scalar loads into SGPRs.  Sequences are
 // sorted by (length, residues), so the 64 patterns of a wave share prefixes
 // and leave a text at nearly the same step.  Pattern = the longer string of
 // the pair when lengths differ (it exits earliest).
@@ -83,9 +89,21 @@ __device__ __forceinline__ uint32_t twice_plus1(uint32_t x) {
   return r;
 }
 
-// kMode: how a lane's remaining miss budget on the final diagonal is held.
-//   1, 2: as wave masks in SGPRs, A_i = lanes whose budget is >= i (k <= kMode)
-//   0:    as a per-lane counter (any k)
+// popcount(z) <= k, with the cheap forms for k = 1 (at most one bit set) and
+// k = 2 (at most two) selected at compile time.
+template <int kMode>
+__device__ __forceinline__ bool within_k_impl(uint32_t z, int k) {
+  if (kMode == 1) return (z & (z - 1u)) == 0u;
+  if (kMode == 2) {
+    const uint32_t y = z & (z - 1u);
+    return (y & (y - 1u)) == 0u;
+  }
+  return __popc(z) <= k;
+}
+#define within_k(z, kk) within_k_impl<kMode>((z), (kk))
+
+// kMode: the within-k test on the miss word: 1 (k = 1), 2 (k = 2), 0 (any k:
+// popcount).
 template <bool kPeqLds, int kMode>
 __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs,
                                                   const uint64_t* __restrict__ item_base,
@@ -140,7 +158,11 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     const uint32_t m = d.m, n = d.n;  // m >= n: the pattern is the longer string
     const uint32_t Mm = low_mask(m);
     const uint32_t delta = m - n;     // final diagonal: row = column + delta
-    const int budget0 = k - (int)delta;  // misses allowed on the final diagonal
+    // Miss word: bit delta+J set when text step J missed on the final
+    // diagonal, bits below delta set from the start, so popcount(Z) is the
+    // diagonal cell D[delta+j][j] after j steps and D[m][n] = lev at the end.
+    // A lane outside the item starts at ~0 (never within k).
+    const uint32_t z_item = lane_ok ? (1u << delta) - 1u : ~0u;
     uint32_t tb = d.t0 + c * T;
     const uint32_t te = min(d.t0 + d.nt, tb + T);
     if (d.tri && tb < gbase + 1) tb = gbase + 1;
@@ -150,48 +172,26 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     while (t < te) {
       const SeqHead tr = load_const(reinterpret_cast<const SeqHead*>(trec), 2 * t);
       uint32_t tn = t + 1;  // next text
-      uint64_t valid = lane_mask;
+      uint32_t Z = z_item;
       bool can_skip = true;
-      if (d.tri) {
-        const uint32_t lim = t - gbase;  // lanes with pattern < text
-        if (lim < 64) {
-          valid &= (1ull << lim) - 1ull;
-          can_skip = false;  // the next texts add valid lanes
-        }
+      if (d.tri && t - gbase < 64u) {
+        if (lane >= t - gbase) Z = ~0u;  // pattern not before the text
+        can_skip = false;                // the next texts add valid lanes
       }
-      // per-text copies the compiler cannot see through, so that the per-step
+      // per-text copy the compiler cannot see through, so that the per-step
       // length tests are formed inside the loop instead of being hoisted
       // into (spilled) registers
       uint32_t nn = n;
       asm volatile("" : "+s"(nn));
-      uint32_t mJ = 1u << delta;  // D0 bit of the final diagonal at the current step
+      uint32_t mJ = 1u << delta;  // diagonal row bit of the current step
       uint32_t ex = 32;           // text step after which no lane was within k (32: none)
 
-      uint64_t A0 = valid, A1 = 0, A2 = 0;
-      int bud = budget0;
-      if (kMode >= 1 && budget0 >= 1) A1 = valid;
-      if (kMode >= 2 && budget0 >= 2) A2 = valid;
-
-// Miss accounting for a text step with zero-step word D0: b = lanes whose
-// step along the final diagonal is zero (D0 bit of the diagonal row set);
-// every other lane spends one unit of budget.  A0 = lanes still within k.
-// The diagonal row moves down one bit per step.
+// Miss accounting for a text step with zero-step word D0; alive: some lane
+// with popcount(Z) <= k.
 #define TCR_MISS(D0)                                                           \
-  if (kMode == 0) {                                                            \
-    bud -= ((D0) & mJ) == 0u ? 1 : 0;                                          \
-    A0 = __ballot(bud >= 0) & valid;                                           \
-  } else {                                                                     \
-    const uint64_t b = __ballot(((D0) & mJ) != 0u);                            \
-    if (kMode >= 2) {                                                          \
-      A0 = (A0 & b) | A1;                                                      \
-      A1 = (A1 & b) | A2;                                                      \
-      A2 &= b;                                                                 \
-    } else {                                                                   \
-      A0 = (A0 & b) | A1;                                                      \
-      A1 &= b;                                                                 \
-    }                                                                          \
-  }                                                                            \
+  Z |= ~(D0) & mJ;                                                             \
   mJ = twice(mJ);
+#define TCR_ALIVE() (__ballot(within_k(Z, k)) != 0ull)
 #define TCR_EQ(cc) (kPeqLds ? wave_eq[(cc) * kWave + lane] : eq[(cc)])
 #define TCR_CODE(q) ((tr.w[(q) / 6] >> (5 * ((q) % 6))) & 31u)
 // Text steps are nested ifs (structured control flow, so every exit stays a
@@ -207,7 +207,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     VN = X & D0;                                                               \
     VP = twice(HN) | ~(X | D0);                                                \
     TCR_MISS(D0)                                                               \
-    if (A0 != 0ull) {
+    if (TCR_ALIVE()) {
 #define TCR_CLOSE(J)                                                           \
     } else {                                                                   \
       ex = (J);                                                                \
@@ -226,7 +226,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
         VP = twice(HN) | ~(X | D0);
         TCR_MISS(D0)
       }
-      if (A0 != 0ull) {
+      if (TCR_ALIVE()) {
         TCR_OPEN(1) TCR_OPEN(2) TCR_OPEN(3) TCR_OPEN(4) TCR_OPEN(5) TCR_OPEN(6) TCR_OPEN(7) TCR_OPEN(8)
         TCR_OPEN(9) TCR_OPEN(10) TCR_OPEN(11) TCR_OPEN(12) TCR_OPEN(13) TCR_OPEN(14) TCR_OPEN(15)
         TCR_OPEN(16) TCR_OPEN(17) TCR_OPEN(18) TCR_OPEN(19) TCR_OPEN(20) TCR_OPEN(21) TCR_OPEN(22)
@@ -247,10 +247,10 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
         // while the set of valid lanes cannot grow)
         if (ex < (uint32_t)kSkipDepths && can_skip) tn = max(load_const(tnxt, 16 * t + ex), t + 1);
       } else {
-        // A0: valid lanes whose final distance D[m][n] = delta + misses <= k
-        const uint64_t hm = A0;
+        // lanes whose final distance D[m][n] = popcount(Z) is within k
+        const bool hit = within_k(Z, k);
+        const uint64_t hm = __ballot(hit);
         if (hm) {
-          const bool hit = (hm >> lane) & 1ull;
           unsigned long long base = 0;
           if (lane == 0) base = atomicAdd(&cnt->edges, (unsigned long long)__popcll(hm));
           base = rfl64(base);
@@ -261,7 +261,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
               e.x = pid;
               e.y = tr.id;
               *reinterpret_cast<uint2*>(edges + 2 * slot) = e;
-              if (edist) edist[slot] = (uint8_t)((int)n + __popc(VP & Mm) - __popc(VN & Mm));
+              if (edist) edist[slot] = (uint8_t)__popc(Z);
             }
           }
         }
@@ -270,6 +270,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
 #undef TCR_OPEN
 #undef TCR_CLOSE
 #undef TCR_MISS
+#undef TCR_ALIVE
 #undef TCR_EQ
 #undef TCR_CODE
     }
@@ -291,7 +292,7 @@ void launch_pairs(const PairArgs& a, uint32_t grid_blocks, bool peq_lds, hipStre
 #define TCR_LAUNCH(LDS, MODE)                                                                              \
   hipLaunchKernelGGL((k_pairs<LDS, MODE>), dim3(grid_blocks), dim3(kBlock), 0, st, a.descs, a.item_base, a.plan, \
                      a.cnt, a.edges, a.edist, a.capacity, a.texts_per_item, a.k)
-  const int mode = a.k <= 1 ? 1 : (a.k == 2 ? 2 : 0);
+  const int mode = a.k == 1 ? 1 : (a.k == 2 ? 2 : 0);
   if (peq_lds) {
     if (mode == 1) TCR_LAUNCH(true, 1);
     else if (mode == 2) TCR_LAUNCH(true, 2);

@@ -32,7 +32,7 @@ def _eq(g, e, d):
     assert np.array_equal(g.degree, d)
 
 
-@pytest.mark.parametrize("k", [0, 1, 2, 3])
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 5, 8, 31])
 def test_small_repertoire_matches_oracle(tn, ctx, orc, k):
     s = synth.small()
     g = tn.tcrnet_build(ctx, s, k)
