@@ -70,8 +70,8 @@ def _bind(lib):
     lib.oracle_exit_steps.argtypes = [_u8p, _u8p, _u8p, _u8p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int,
                                       ctypes.c_void_p]
     lib.wm_items.restype = None
-    lib.wm_items.argtypes = [_u8p, _u8p, _u8p, _u8p, _u8p, ctypes.c_int64, ctypes.c_int, ctypes.c_void_p,
-                             ctypes.c_void_p]
+    lib.wm_items.argtypes = [_u8p, _u8p, _u8p, _u8p, _u8p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
+                             ctypes.c_void_p, ctypes.c_void_p]
     lib.k1_build.restype = ctypes.c_int
     lib.k1_build.argtypes = [_u8p, _u8p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p),
                              ctypes.POINTER(ctypes.c_uint64), ctypes.c_void_p]
@@ -184,10 +184,11 @@ class Oracle:
                                    len(pi), k, self.nthreads, out.ctypes.data)
         return out[:len(pi)]
 
-    def work_items(self, seqs, seq, gend, items, k: int):
+    def work_items(self, seqs, seq, gend, items, k: int, resume: int = 0):
         """Work model: (text steps, texts visited) of each work item
         (rows of items: gbase, np, tb, te, tri over sorted positions; seq:
-        sorted position -> input id; gend: n x 8 prefix-group ends)."""
+        sorted position -> input id; gend: n x 8 prefix-group ends; resume:
+        steps a visited text can take over from the previous one)."""
         seq = np.ascontiguousarray(seq, dtype=np.uint32)
         gend = np.ascontiguousarray(gend, dtype=np.uint32)
         items = np.ascontiguousarray(items, dtype=np.uint32).reshape(-1, 5)
@@ -195,7 +196,7 @@ class Oracle:
         texts = np.zeros(max(1, len(items)), dtype=np.uint64)
         chars = np.ascontiguousarray(seqs.chars) if seqs.chars.size else np.zeros(1, np.uint8)
         self.lib.wm_items(chars.ctypes.data, seqs.offsets.ctypes.data, seq.ctypes.data, gend.ctypes.data,
-                          items.ctypes.data, len(items), k, steps.ctypes.data, texts.ctypes.data)
+                          items.ctypes.data, len(items), k, resume, steps.ctypes.data, texts.ctypes.data)
         return steps[:len(items)], texts[:len(items)]
 
     def k1_build(self, seqs):

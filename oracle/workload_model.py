@@ -10,8 +10,10 @@ For each workload it records
     longer string; computed from the oracle's full DP table, see
     oracle_exit_step), with its standard error -- the per-pair work;
   * wave_steps: the text steps of the pair kernel's traversal, where a wave
-    of 64 patterns walks the lexicographically sorted texts of a work item
-    and jumps past every prefix group on which all its lanes ended early
+    of 64 patterns walks the lexicographically sorted texts of a work item,
+    jumps past every prefix group on which all its lanes ended early, and
+    starts each visited text after the residues it shares with the previous
+    one (up to RESUME of them)
     (replayed by workmodel.c from the oracle's exit steps over a seeded
     uniform sample of work items, or all items when few), with the number of
     visited texts and the standard error.
@@ -82,6 +84,7 @@ def sample_pairs(lengths: np.ndarray, k: int, n_samples: int, seed: int):
 ALPHABET = "ARNDCQEGHILKMFPSTWYV"
 SORT_RESIDUES = 11   # residues in the sort key of a one-segment build
 DEPTHS = 8           # prefix depths with a group end
+RESUME = 6           # text steps a visited text can take over from the previous one
 WAVE = 64
 
 
@@ -168,7 +171,7 @@ def plan_items(L_sorted, k: int, T: int) -> np.ndarray:
     return np.concatenate(rows).astype(np.uint32)
 
 
-def traversal(seqs, k: int, T: int, max_items: int, seed: int = 1) -> dict:
+def traversal(seqs, k: int, T: int, max_items: int, seed: int = 1, resume: int = RESUME) -> dict:
     """Text steps and visited texts of the traversal over all work items
     (exact when the items number at most max_items, else estimated from a
     seeded uniform sample of max_items items)."""
@@ -182,11 +185,11 @@ def traversal(seqs, k: int, T: int, max_items: int, seed: int = 1) -> dict:
         pick = items
     else:
         pick = items[np.random.default_rng(seed).choice(total, size=max_items, replace=False)]
-    steps, texts = oracle.Oracle().work_items(seqs, order, gend, pick, k)
+    steps, texts = oracle.Oracle().work_items(seqs, order, gend, pick, k, resume)
     steps = steps.astype(np.float64)
     texts = texts.astype(np.float64)
     scale = total / max(1, len(pick))
-    out = {"texts_per_item": T, "items": total, "items_modelled": int(len(pick)), "exact": bool(exact),
+    out = {"texts_per_item": T, "resume_depth": resume, "items": total, "items_modelled": int(len(pick)), "exact": bool(exact),
            "wave_steps": float(steps.sum() * scale), "visited_texts": float(texts.sum() * scale)}
     out["stderr_wave_steps"] = 0.0 if exact else float(steps.std(ddof=1) * total / np.sqrt(len(pick)))
     return out

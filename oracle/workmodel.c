@@ -11,7 +11,10 @@
  * residues, all texts sharing those first e residues end the same way, so
  * the walk continues at the end of that prefix group (group ends for
  * e = 1..8, given by the caller); in a triangle item this holds only once all
- * 64 lanes are valid (pattern before text).
+ * 64 lanes are valid (pattern before text).  A visited text whose first r
+ * residues equal those of the previous visited text of the item starts at
+ * step r (r capped at `resume`; 0 for the item's first text and after a text
+ * whose set of valid lanes differs from the next one's).
  */
 #include <stdint.h>
 
@@ -20,14 +23,25 @@ int oracle_exit_step(const uint8_t* a, int m, const uint8_t* b, int n, int k);
 
 #define WM_DEPTHS 8
 
+/* Length of the common prefix of a and b (n residues each), at most cap. */
+static int common_prefix(const uint8_t* a, const uint8_t* b, int n, int cap) {
+  int q = 0;
+  while (q < n && q < cap && a[q] == b[q]) ++q;
+  return q;
+}
+
 /* One item: patterns at sorted positions [gbase, gbase + np), texts [tb, te),
  * tri: only pairs with pattern position < text position.  seq[s] = input id
  * of sorted position s; gend[s * 8 + d - 1] = end of s's depth-d prefix
  * group.  Returns the text steps; *texts = texts visited. */
+
 static uint64_t wm_item(const uint8_t* chars, const uint64_t* offsets, const uint32_t* seq, const uint32_t* gend,
-                        uint32_t gbase, uint32_t np, uint32_t tb, uint32_t te, int tri, int k, uint64_t* texts) {
+                        uint32_t gbase, uint32_t np, uint32_t tb, uint32_t te, int tri, int k, int resume,
+                        uint64_t* texts) {
   uint64_t steps = 0, visited = 0;
   uint32_t t = tb;
+  int prev_ok = 0;       /* previous visited text may pass its state on */
+  uint32_t prev = 0;
   while (t < te) {
     const uint32_t b = seq[t];
     const uint8_t* tb_ = chars + offsets[b];
@@ -42,9 +56,16 @@ static uint64_t wm_item(const uint8_t* chars, const uint64_t* offsets, const uin
       if (s == n && oracle_lev(pa, m, tb_, n) <= k) full = 1;
       if (s > e) e = s;
     }
-    steps += full ? (uint64_t)n : (uint64_t)e;
+    int r = 0;
+    if (prev_ok) {
+      r = common_prefix(chars + offsets[seq[prev]], tb_, n, WM_DEPTHS);
+      if (r > resume) r = resume;
+    }
+    steps += (full ? (uint64_t)n : (uint64_t)e) - (uint64_t)r;
     visited += 1;
     const int can_skip = !tri || t - gbase >= 64;
+    prev_ok = can_skip;
+    prev = t;
     uint32_t tn = t + 1;
     if (!full && e >= 1 && e <= WM_DEPTHS && can_skip) {
       tn = gend[(uint64_t)t * WM_DEPTHS + (uint64_t)(e - 1)];
@@ -58,10 +79,10 @@ static uint64_t wm_item(const uint8_t* chars, const uint64_t* offsets, const uin
 
 /* count items, item q = (gbase, np, tb, te, tri) at items[5q..5q+4]. */
 void wm_items(const uint8_t* chars, const uint64_t* offsets, const uint32_t* seq, const uint32_t* gend,
-              const uint32_t* items, int64_t count, int k, uint64_t* steps, uint64_t* texts) {
+              const uint32_t* items, int64_t count, int k, int resume, uint64_t* steps, uint64_t* texts) {
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t q = 0; q < count; ++q) {
     const uint32_t* it = items + 5 * q;
-    steps[q] = wm_item(chars, offsets, seq, gend, it[0], it[1], it[2], it[3], (int)it[4], k, &texts[q]);
+    steps[q] = wm_item(chars, offsets, seq, gend, it[0], it[1], it[2], it[3], (int)it[4], k, resume, &texts[q]);
   }
 }

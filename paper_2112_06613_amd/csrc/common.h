@@ -12,11 +12,15 @@ constexpr int kBlock = 256;      // threads per block of the pair kernel (4 wave
 constexpr uint32_t kQueryTag = 0x80000000u;  // id bit marking the query side
 
 constexpr int kSkipDepths = 8;   // prefix depths with a group-end pointer
+constexpr uint32_t kLenMask = 63u;  // length bits of SeqRec::len
 
 // One sequence as the pair kernel reads it (64 bytes, read with one scalar
 // load when the sequence is the wave-uniform text).
 //   w[0..5]: 5-bit residue codes, 6 per word, code q in w[q/6] bits 5*(q%6)
-//   len:     number of residues (1..32)
+//   len:     bits 0-5: number of residues (1..32); in sorted records also
+//            bits 6-9: common prefix length (capped at 8) with the next
+//            sorted record, and for d = 2..8 bits 10+3(d-2) .. +2: common
+//            prefix length with nxt[d-1] (below d)
 //   id:      caller-visible node id (input position; in query mode the query
 //            side carries kQueryTag)
 //   nxt[d-1] (sorted records only): the first sorted position after this one
@@ -94,14 +98,23 @@ struct Plan {
   uint32_t pad;
 };
 
-// Work counters of one build (zeroed before the encode kernel).
-struct Counters {
-  unsigned long long item_next;   // next work item to hand out
+// Work counters of one build (zeroed before the encode kernel).  Every wave
+// takes work items with atomics, so the queue is split into kQueueStripes
+// counters (stripe s hands out items s, s + kQueueStripes, ...), each on a
+// cache line of its own, and the edge counter sits on another: the atomics
+// of thousands of waves do not serialise on one line.
+constexpr int kQueueStripes = 16;
+struct alignas(128) QueueLine {
+  unsigned long long next;        // next index j of this stripe
+  unsigned long long pad[15];
+};
+struct alignas(256) Counters {
+  QueueLine queue[kQueueStripes];
   unsigned long long edges;       // edges found (may exceed the capacity)
   unsigned long long err;         // min over bad inputs of (index << 2 | code),
                                   // code 1: residue outside the alphabet,
                                   // code 2: length 0 or > 32; ~0: none
-  unsigned long long pad;
+  unsigned long long pad1[14];
 };
 constexpr unsigned long long kNoError = ~0ull;
 

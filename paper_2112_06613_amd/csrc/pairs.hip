@@ -40,6 +40,8 @@ namespace tcr {
 
 namespace {
 
+constexpr int kEdgeBuf = 128;  // staged edges per wave
+
 __device__ __forceinline__ uint32_t rfl(uint32_t v) { return __builtin_amdgcn_readfirstlane(v); }
 
 __device__ __forceinline__ uint64_t rfl64(uint64_t v) {
@@ -111,18 +113,52 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
                                                   uint32_t* __restrict__ edges, uint8_t* __restrict__ edist,
                                                   uint64_t capacity, uint32_t T, int k) {
   __shared__ uint32_t lds_eq[kPeqLds ? (kBlock / kWave) * kAlpha * kWave : 1];
+  // per-wave edge staging: hits collect here and take their global slots
+  // with one atomic per kEdgeBuf edges instead of one per hitting text
+  __shared__ uint2 lds_edge[kBlock / kWave][kEdgeBuf];
+  __shared__ uint8_t lds_dist[kBlock / kWave][kEdgeBuf];
   const uint32_t lane = threadIdx.x & 63u;
   const uint32_t wid = threadIdx.x >> 6;
   const uint64_t total = plan->total_items;
   const uint32_t nd = plan->n_desc;
   const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
   uint32_t* wave_eq = lds_eq + (kPeqLds ? wid * kAlpha * kWave : 0);
+  uint2* wave_edge = lds_edge[wid];
+  uint8_t* wave_dist = lds_dist[wid];
+  uint32_t staged = 0;  // edges in wave_edge (wave-uniform)
 
+  // Move the staged edges to consecutive global slots (one atomic per wave).
+  auto flush = [&]() {
+    __builtin_amdgcn_wave_barrier();
+    unsigned long long base = 0;
+    if (lane == 0) base = atomicAdd(&cnt->edges, (unsigned long long)staged);
+    base = rfl64(base);
+    for (uint32_t i = lane; i < staged; i += kWave) {
+      const uint64_t slot = base + i;
+      if (slot < capacity) {
+        *reinterpret_cast<uint2*>(edges + 2 * slot) = wave_edge[i];
+        if (edist) edist[slot] = wave_dist[i];
+      }
+    }
+    __builtin_amdgcn_wave_barrier();
+    staged = 0;
+  };
+
+  // a wave starts on its own queue stripe and moves on when it runs dry; it
+  // stops after finding every stripe empty in a row
+  uint32_t stripe = (blockIdx.x * (kBlock / kWave) + rfl(wid)) % kQueueStripes;
+  uint32_t empty = 0;
   for (;;) {
-    uint64_t item = 0;
-    if (lane == 0) item = atomicAdd(&cnt->item_next, 1ull);
-    item = rfl64(item);
-    if (item >= total) break;
+    uint64_t j = 0;
+    if (lane == 0) j = atomicAdd(&cnt->queue[stripe].next, 1ull);
+    j = rfl64(j);
+    const uint64_t item = j * kQueueStripes + stripe;
+    if (item >= total) {
+      if (++empty == (uint32_t)kQueueStripes) break;
+      stripe = (stripe + 1) % kQueueStripes;
+      continue;
+    }
+    empty = 0;
 
     // descriptor holding this item: largest di with item_base[di] <= item
     uint32_t lo = 0, hi = nd;
@@ -167,38 +203,43 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     const uint32_t te = min(d.t0 + d.nt, tb + T);
     if (d.tri && tb < gbase + 1) tb = gbase + 1;
 
+    // Register stack of the state after each of the first kDepth text steps.
+    // Texts are visited in sorted order, so a text sharing its first r
+    // residues with the previous visited text resumes at step r from the
+    // stored state (a depth-first walk over the implicit prefix tree of the
+    // sorted texts); r = 0 for an item's first text and whenever the set of
+    // valid lanes changes.
+    constexpr int kDepth = 6;
+    uint32_t sVP[kDepth], sVN[kDepth], sZ[kDepth];
+    uint32_t r = 0;
+
     const uint32_t* tnxt = reinterpret_cast<const uint32_t*>(trec) + 8;  // nxt[] of record 0
     uint32_t t = tb;
     while (t < te) {
       const SeqHead tr = load_const(reinterpret_cast<const SeqHead*>(trec), 2 * t);
       uint32_t tn = t + 1;  // next text
-      uint32_t Z = z_item;
+      uint32_t z_text = z_item;
       bool can_skip = true;
       if (d.tri && t - gbase < 64u) {
-        if (lane >= t - gbase) Z = ~0u;  // pattern not before the text
-        can_skip = false;                // the next texts add valid lanes
+        if (lane >= t - gbase) z_text = ~0u;  // pattern not before the text
+        can_skip = false;                     // the next texts add valid lanes
       }
-      // per-text copy the compiler cannot see through, so that the per-step
-      // length tests are formed inside the loop instead of being hoisted
-      // into (spilled) registers
-      uint32_t nn = n;
-      asm volatile("" : "+s"(nn));
-      uint32_t mJ = 1u << delta;  // diagonal row bit of the current step
-      uint32_t ex = 32;           // text step after which no lane was within k (32: none)
+      // per-text copies the compiler cannot see through, so that the per-step
+      // length and resume tests are formed inside the loop instead of being
+      // hoisted into (spilled) registers
+      uint32_t nn = n, rr = r;
+      asm volatile("" : "+s"(nn), "+s"(rr));
+      uint32_t mJ = (1u << delta) << rr;  // diagonal row bit of the first computed step
+      uint32_t ex = 32;                    // text step after which no lane was within k (32: none)
+      bool alive = true;
+      uint32_t VP = Mm, VN = 0, Z = z_text;
 
-// Miss accounting for a text step with zero-step word D0; alive: some lane
-// with popcount(Z) <= k.
-#define TCR_MISS(D0)                                                           \
-  Z |= ~(D0) & mJ;                                                             \
-  mJ = twice(mJ);
-#define TCR_ALIVE() (__ballot(within_k(Z, k)) != 0ull)
+// One Myers/Hyyro text step on character J, then the miss accounting: OR the
+// diagonal row's miss bit into Z; alive: some lane with popcount(Z) <= k.
 #define TCR_EQ(cc) (kPeqLds ? wave_eq[(cc) * kWave + lane] : eq[(cc)])
 #define TCR_CODE(q) ((tr.w[(q) / 6] >> (5 * ((q) % 6))) & 31u)
-// Text steps are nested ifs (structured control flow, so every exit stays a
-// plain scalar branch): step J runs only while J < n and some lane is still
-// within k; a wave with none left records the step in ex.
-#define TCR_OPEN(J)                                                            \
-  if ((uint32_t)(J) < nn) {                                                    \
+#define TCR_CORE(J)                                                            \
+  {                                                                            \
     const uint32_t Eq = TCR_EQ(TCR_CODE(J));                                   \
     const uint32_t D0 = (((Eq & VP) + VP) ^ VP) | Eq | VN;                     \
     const uint32_t HP = VN | ~(D0 | VP);                                       \
@@ -206,76 +247,103 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     const uint32_t X = twice_plus1(HP);                                        \
     VN = X & D0;                                                               \
     VP = twice(HN) | ~(X | D0);                                                \
-    TCR_MISS(D0)                                                               \
-    if (TCR_ALIVE()) {
+    Z |= ~D0 & mJ;                                                             \
+    mJ = twice(mJ);                                                            \
+    alive = __ballot(within_k(Z, k)) != 0ull;                                  \
+  }
+#define TCR_SLOT(J) ((J) < kDepth ? (J) : 0)
+// Text steps are nested ifs (structured control flow, so every exit stays a
+// plain scalar or VCC branch): step J runs only while J < n and some lane is
+// still within k; a wave with none left records the step in ex.  Steps below
+// kDepth take their input from stack slot J-1 (or the first column) and keep
+// their output in slot J, unless reused from the previous text (J < r).
+#define TCR_OPEN(J)                                                            \
+  if ((uint32_t)(J) < nn) {                                                    \
+    if constexpr ((J) < kDepth) {                                              \
+      if ((uint32_t)(J) >= rr) {                                               \
+        if constexpr ((J) > 0) {                                               \
+          VP = sVP[TCR_SLOT((J) - 1)];                                         \
+          VN = sVN[TCR_SLOT((J) - 1)];                                         \
+          Z = sZ[TCR_SLOT((J) - 1)];                                           \
+        }                                                                      \
+        TCR_CORE(J)                                                            \
+        sVP[TCR_SLOT(J)] = VP;                                                 \
+        sVN[TCR_SLOT(J)] = VN;                                                 \
+        sZ[TCR_SLOT(J)] = Z;                                                   \
+      }                                                                        \
+    } else {                                                                   \
+      if constexpr ((J) == kDepth) {                                           \
+        VP = sVP[kDepth - 1];                                                  \
+        VN = sVN[kDepth - 1];                                                  \
+        Z = sZ[kDepth - 1];                                                    \
+      }                                                                        \
+      TCR_CORE(J)                                                              \
+    }                                                                          \
+    if (alive) {
 #define TCR_CLOSE(J)                                                           \
     } else {                                                                   \
       ex = (J);                                                                \
     }                                                                          \
   }
 
-      // text step for character 0, from VP = 1^m, VN = 0 (then Eq & VP = Eq)
-      uint32_t VP, VN;
-      {
-        const uint32_t Eq = TCR_EQ(TCR_CODE(0));
-        const uint32_t D0 = ((Eq + Mm) ^ Mm) | Eq;
-        const uint32_t HP = ~(D0 | Mm);
-        const uint32_t HN = D0 & Mm;
-        const uint32_t X = twice_plus1(HP);
-        VN = X & D0;
-        VP = twice(HN) | ~(X | D0);
-        TCR_MISS(D0)
-      }
-      if (TCR_ALIVE()) {
-        TCR_OPEN(1) TCR_OPEN(2) TCR_OPEN(3) TCR_OPEN(4) TCR_OPEN(5) TCR_OPEN(6) TCR_OPEN(7) TCR_OPEN(8)
-        TCR_OPEN(9) TCR_OPEN(10) TCR_OPEN(11) TCR_OPEN(12) TCR_OPEN(13) TCR_OPEN(14) TCR_OPEN(15)
-        TCR_OPEN(16) TCR_OPEN(17) TCR_OPEN(18) TCR_OPEN(19) TCR_OPEN(20) TCR_OPEN(21) TCR_OPEN(22)
-        TCR_OPEN(23) TCR_OPEN(24) TCR_OPEN(25) TCR_OPEN(26) TCR_OPEN(27) TCR_OPEN(28) TCR_OPEN(29)
-        TCR_OPEN(30) TCR_OPEN(31)
-        TCR_CLOSE(31) TCR_CLOSE(30) TCR_CLOSE(29) TCR_CLOSE(28) TCR_CLOSE(27) TCR_CLOSE(26)
-        TCR_CLOSE(25) TCR_CLOSE(24) TCR_CLOSE(23) TCR_CLOSE(22) TCR_CLOSE(21) TCR_CLOSE(20)
-        TCR_CLOSE(19) TCR_CLOSE(18) TCR_CLOSE(17) TCR_CLOSE(16) TCR_CLOSE(15) TCR_CLOSE(14)
-        TCR_CLOSE(13) TCR_CLOSE(12) TCR_CLOSE(11) TCR_CLOSE(10) TCR_CLOSE(9) TCR_CLOSE(8)
-        TCR_CLOSE(7) TCR_CLOSE(6) TCR_CLOSE(5) TCR_CLOSE(4) TCR_CLOSE(3) TCR_CLOSE(2) TCR_CLOSE(1)
-      } else {
-        ex = 0;
-      }
+      TCR_OPEN(0) TCR_OPEN(1) TCR_OPEN(2) TCR_OPEN(3) TCR_OPEN(4) TCR_OPEN(5) TCR_OPEN(6) TCR_OPEN(7)
+      TCR_OPEN(8) TCR_OPEN(9) TCR_OPEN(10) TCR_OPEN(11) TCR_OPEN(12) TCR_OPEN(13) TCR_OPEN(14)
+      TCR_OPEN(15) TCR_OPEN(16) TCR_OPEN(17) TCR_OPEN(18) TCR_OPEN(19) TCR_OPEN(20) TCR_OPEN(21)
+      TCR_OPEN(22) TCR_OPEN(23) TCR_OPEN(24) TCR_OPEN(25) TCR_OPEN(26) TCR_OPEN(27) TCR_OPEN(28)
+      TCR_OPEN(29) TCR_OPEN(30) TCR_OPEN(31)
+      TCR_CLOSE(31) TCR_CLOSE(30) TCR_CLOSE(29) TCR_CLOSE(28) TCR_CLOSE(27) TCR_CLOSE(26)
+      TCR_CLOSE(25) TCR_CLOSE(24) TCR_CLOSE(23) TCR_CLOSE(22) TCR_CLOSE(21) TCR_CLOSE(20)
+      TCR_CLOSE(19) TCR_CLOSE(18) TCR_CLOSE(17) TCR_CLOSE(16) TCR_CLOSE(15) TCR_CLOSE(14)
+      TCR_CLOSE(13) TCR_CLOSE(12) TCR_CLOSE(11) TCR_CLOSE(10) TCR_CLOSE(9) TCR_CLOSE(8)
+      TCR_CLOSE(7) TCR_CLOSE(6) TCR_CLOSE(5) TCR_CLOSE(4) TCR_CLOSE(3) TCR_CLOSE(2) TCR_CLOSE(1)
+      TCR_CLOSE(0)
 
+      // common prefix of this text with the next visited one (from the
+      // record's packed lengths): the steps the next text can reuse
+      uint32_t lcp_next = (tr.len >> 6) & 15u;
       if (ex < 32) {
         // every text sharing this text's first ex+1 residues ends at the same
         // step with no lane within k: jump past that prefix group (possible
         // while the set of valid lanes cannot grow)
-        if (ex < (uint32_t)kSkipDepths && can_skip) tn = max(load_const(tnxt, 16 * t + ex), t + 1);
+        if (ex < (uint32_t)kSkipDepths && can_skip) {
+          tn = max(load_const(tnxt, 16 * t + ex), t + 1);
+          lcp_next = ex == 0 ? 0u : (tr.len >> (10 + 3 * (ex - 1))) & 7u;
+        }
       } else {
+        // all n steps ran: the state after step n-1 (stack slot or rolling)
+        uint32_t fZ = Z;
+#pragma unroll
+        for (int q = 0; q < kDepth; ++q)
+          if (n == (uint32_t)q + 1) fZ = sZ[q];
         // lanes whose final distance D[m][n] = popcount(Z) is within k
-        const bool hit = within_k(Z, k);
+        const bool hit = within_k(fZ, k);
         const uint64_t hm = __ballot(hit);
         if (hm) {
-          unsigned long long base = 0;
-          if (lane == 0) base = atomicAdd(&cnt->edges, (unsigned long long)__popcll(hm));
-          base = rfl64(base);
+          const uint32_t nh = (uint32_t)__popcll(hm);
+          if (staged + nh > (uint32_t)kEdgeBuf) flush();
           if (hit) {
-            const uint64_t slot = base + (uint64_t)__popcll(hm & lt_mask);
-            if (slot < capacity) {
-              uint2 e;
-              e.x = pid;
-              e.y = tr.id;
-              *reinterpret_cast<uint2*>(edges + 2 * slot) = e;
-              if (edist) edist[slot] = (uint8_t)__popc(Z);
-            }
+            const uint32_t pos = staged + (uint32_t)__popcll(hm & lt_mask);
+            uint2 e;
+            e.x = pid;
+            e.y = tr.id;
+            wave_edge[pos] = e;
+            wave_dist[pos] = (uint8_t)__popc(fZ);
           }
+          staged += nh;
         }
       }
+      r = can_skip ? min(lcp_next, (uint32_t)kDepth) : 0u;
       t = tn;
 #undef TCR_OPEN
 #undef TCR_CLOSE
-#undef TCR_MISS
-#undef TCR_ALIVE
+#undef TCR_SLOT
+#undef TCR_CORE
 #undef TCR_EQ
 #undef TCR_CODE
     }
     if (kPeqLds) __builtin_amdgcn_wave_barrier();
   }
+  if (staged) flush();
 }
 
 }  // namespace

@@ -64,7 +64,7 @@ hipError_t pipeline_reserve(Pipeline& pl, uint64_t n, uint32_t n_seg, int k, uin
   TCR_RESERVE(pl.off, ((uint64_t)n_seg * 64 + 1) * 4);
   TCR_RESERVE(pl.descs, (uint64_t)max_desc * sizeof(Desc));
   TCR_RESERVE(pl.ibase, (uint64_t)max_desc * 8);
-  TCR_RESERVE(pl.meta, 128);
+  TCR_RESERVE(pl.meta, sizeof(Counters) + sizeof(Plan) + 64);
   const uint64_t tw = radix_tmp_words(nn > cap ? nn : cap);
   TCR_RESERVE(pl.tmp, tw * 4);
   TCR_RESERVE(pl.edges, cap * 8);

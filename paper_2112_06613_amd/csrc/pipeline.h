@@ -48,7 +48,7 @@ struct Pipeline {
   uint64_t n_cap = 0, e_cap = 0;
   uint32_t desc_cap = 0;
   Counters* cnt() const { return meta.as<Counters>(); }
-  Plan* plan() const { return reinterpret_cast<Plan*>(meta.as<char>() + 64); }
+  Plan* plan() const { return reinterpret_cast<Plan*>(meta.as<char>() + sizeof(Counters)); }
 };
 
 struct Meta {  // host copy of the counters and plan header

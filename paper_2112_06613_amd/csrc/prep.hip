@@ -26,19 +26,16 @@ __global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
 }
 
 __global__ void k_reset_counters(Counters* c) {
+  if (threadIdx.x < kQueueStripes) c->queue[threadIdx.x].next = 0;
   if (threadIdx.x == 0) {
-    c->item_next = 0;
     c->edges = 0;
     c->err = kNoError;
-    c->pad = 0;
   }
 }
 
 __global__ void k_reset_work(Counters* c) {
-  if (threadIdx.x == 0) {
-    c->item_next = 0;
-    c->edges = 0;
-  }
+  if (threadIdx.x < kQueueStripes) c->queue[threadIdx.x].next = 0;
+  if (threadIdx.x == 0) c->edges = 0;
 }
 
 __global__ void k_record_keys(const SeqRec* __restrict__ rec, uint32_t n, int nres, int len_shift,
@@ -50,11 +47,11 @@ __global__ void k_record_keys(const SeqRec* __restrict__ rec, uint32_t n, int nr
 #pragma unroll
   for (int q = 0; q < 12; ++q) {
     if (q < nres) {
-      const uint32_t c = q < (int)r.len ? (r.w[q / 6] >> (5 * (q % 6))) & 31u : 0u;
+      const uint32_t c = q < (int)(r.len & kLenMask) ? (r.w[q / 6] >> (5 * (q % 6))) & 31u : 0u;
       lex |= (uint64_t)c << (5 * (nres - 1 - q));
     }
   }
-  key[i] = ((uint64_t)r.len << len_shift) | lex;
+  key[i] = ((uint64_t)(r.len & kLenMask) << len_shift) | lex;
   val[i] = i;
 }
 
@@ -152,6 +149,22 @@ __global__ void k_gather(const SeqRec* __restrict__ rec, const uint32_t* __restr
     }
     r.nxt[d - 1] = (uint32_t)hi;
   }
+  // common prefix lengths with the next record and with each group end: the
+  // groups are nested, so a position lies in the depth-d group of s exactly
+  // when it is below nxt[d-1]
+  uint32_t packed = r.len & kLenMask;
+  uint32_t l_next = 0;
+#pragma unroll
+  for (int d = 1; d <= kSkipDepths; ++d) l_next += r.nxt[d - 1] > s + 1 ? 1u : 0u;
+  packed |= l_next << 6;
+#pragma unroll
+  for (int d = 2; d <= kSkipDepths; ++d) {
+    uint32_t l = 0;
+#pragma unroll
+    for (int q = 1; q < d; ++q) l += r.nxt[q - 1] > r.nxt[d - 1] ? 1u : 0u;
+    packed |= l << (10 + 3 * (d - 2));
+  }
+  r.len = packed;
   srec[s] = r;
   // bit planes of the residue codes, then Peq[c] = positions whose code is c
   uint32_t pl[5] = {0, 0, 0, 0, 0};
@@ -161,7 +174,8 @@ __global__ void k_gather(const SeqRec* __restrict__ rec, const uint32_t* __restr
 #pragma unroll
     for (int b = 0; b < 5; ++b) pl[b] |= ((c >> b) & 1u) << q;
   }
-  const uint32_t lm = r.len >= 32 ? ~0u : ((1u << r.len) - 1u);
+  const uint32_t len = r.len & kLenMask;
+  const uint32_t lm = len >= 32 ? ~0u : ((1u << len) - 1u);
   PeqRec p;
 #pragma unroll
   for (int c = 0; c < kAlpha; ++c) {

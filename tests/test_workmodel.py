@@ -37,19 +37,26 @@ def test_sorted_order_and_group_ends():
 def test_walk_is_exact_and_matches_python(orc, k):
     s, L, order, gend, items = _setup(500, 128, k, 9 + k)
     strs = s.to_list()
-    steps_c, texts_c = orc.work_items(s, order, gend, items, k)
+    steps_c, texts_c = orc.work_items(s, order, gend, items, k, wm.RESUME)
     skipped = 0
     for q, (gbase, npat, tb, te, tri) in enumerate(items.tolist()):
         steps = visited = 0
         t = tb
+        prev = None
         while t < te:
             b = strs[order[t]]
             lanes = [p for p in range(gbase, gbase + npat) if not (tri and p >= t)]
             ex = [orc.exit_step(strs[order[p]], b, k) for p in lanes]
             full = any(orc.lev(strs[order[p]], b) <= k for p in lanes)
             e = max(ex)
-            steps += len(b) if full else e
+            r = 0
+            if prev is not None:
+                a = strs[order[prev]]
+                while r < min(len(b), wm.RESUME) and a[r] == b[r]:
+                    r += 1
+            steps += (len(b) if full else e) - r
             visited += 1
+            prev = t if (not tri or t - gbase >= 64) else None
             tn = t + 1
             if not full and e <= wm.DEPTHS and (not tri or t - gbase >= 64):
                 tn = max(int(gend[t, e - 1]), t + 1)
