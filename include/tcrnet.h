@@ -61,6 +61,9 @@ extern "C" {
 
 #define TCRNET_MAX_LEN 32
 #define TCRNET_MAX_K 31
+/* Largest sequence set: one build's input (all repertoires of a batched
+ * build together), and a serving index including every insert. */
+#define TCRNET_MAX_SEQS (1u << 28)
 
 typedef struct tcrnet_ctx tcrnet_ctx;
 typedef struct tcrnet_graph tcrnet_graph;
@@ -78,7 +81,7 @@ typedef struct {
 /* Options; a zero field selects the default.  Pass NULL for all defaults. */
 typedef struct {
   uint32_t texts_per_item;  /* texts per work item of the pair kernel
-                               (0: autotuned table / 4096 for builds,
+                               (0: autotuned table / 16384 for builds,
                                1024 for a serving index) */
   uint32_t waves_per_simd;  /* resident waves per SIMD of the persistent
                                pair kernel (0: 8) */

@@ -195,7 +195,7 @@ def traversal(seqs, k: int, T: int, max_items: int, seed: int = 1, resume: int =
     return out
 
 
-def model(seqs, k: int, n_samples: int, seed: int = 1, T: int = 4096, max_items: int = 1 << 20) -> dict:
+def model(seqs, k: int, n_samples: int, seed: int = 1, T: int = 16384, max_items: int = 1 << 20) -> dict:
     lengths = seqs.lengths()
     pi, pj, evaluated = sample_pairs(lengths, k, n_samples, seed)
     steps = oracle.Oracle().exit_steps(seqs, pi, pj, k).astype(np.float64)

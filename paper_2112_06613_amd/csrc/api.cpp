@@ -36,6 +36,7 @@ int32_t check_k(int32_t k) {
 // offset monotonicity (lengths themselves are validated on the device).
 int32_t check_host_seqs(const tcrnet_seqs* s, const char* what) {
   if (!s) return set_error(TCRNET_EINVAL, "%s: NULL sequence set", what);
+  if (s->n > TCRNET_MAX_SEQS) return set_error(TCRNET_EINVAL, "%s: more than 2^28 sequences", what);
   if (s->n && (!s->offsets || !s->data)) return set_error(TCRNET_EINVAL, "%s: NULL data or offsets", what);
   for (uint32_t i = 0; i < s->n; ++i)
     if (s->offsets[i + 1] < s->offsets[i])
@@ -248,8 +249,6 @@ int32_t tcrnet_build(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k, tcrnet
 
 int32_t tcrnet_build_weighted(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k_max, tcrnet_graph** out) {
   if (out) *out = nullptr;
-  if (seqs && seqs->n > (1u << 29))
-    return set_error(TCRNET_EINVAL, "weighted builds take at most 2^29 sequences");
   return build_host(ctx, seqs, k_max, true, out);
 }
 
@@ -268,6 +267,7 @@ int32_t tcrnet_build_device(tcrnet_ctx* ctx, const char* d_data, const uint64_t*
   if (!ctx || !n_edges) return set_error(TCRNET_EINVAL, "NULL context or n_edges");
   int32_t rc;
   if ((rc = check_k(k))) return rc;
+  if (n > TCRNET_MAX_SEQS) return set_error(TCRNET_EINVAL, "more than 2^28 sequences");
   if (n && (!d_data || !d_offsets || !d_degree)) return set_error(TCRNET_EINVAL, "NULL device buffer");
   if (pair_capacity && !d_pairs) return set_error(TCRNET_EINVAL, "NULL pair buffer with nonzero capacity");
   (void)hipSetDevice(ctx->device);
@@ -332,7 +332,7 @@ int32_t tcrnet_build_batch(tcrnet_ctx* ctx, const tcrnet_seqs* reps, uint32_t n_
   uint64_t bytes = 0, total = 0;
   for (uint32_t r = 0; r < n_reps; ++r) {
     total += reps[r].n;
-    if (total > 0xffffffffull) return set_error(TCRNET_EINVAL, "more than 2^32-1 sequences in one batch");
+    if (total > TCRNET_MAX_SEQS) return set_error(TCRNET_EINVAL, "more than 2^28 sequences in one batch");
     seg[r + 1] = (uint32_t)total;
     if (reps[r].n) bytes += reps[r].offsets[reps[r].n] - reps[r].offsets[0];
   }

@@ -189,7 +189,6 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
       for (int a = 0; a < kAlpha; ++a) wave_eq[a * kWave + lane] = eq[a];
       __builtin_amdgcn_wave_barrier();
     }
-    const uint32_t pid = load_global(prec, p).id;
 
     const uint32_t m = d.m, n = d.n;  // m >= n: the pattern is the longer string
     const uint32_t Mm = low_mask(m);
@@ -324,7 +323,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
           if (hit) {
             const uint32_t pos = staged + (uint32_t)__popcll(hm & lt_mask);
             uint2 e;
-            e.x = pid;
+            e.x = load_global(reinterpret_cast<const uint32_t*>(prec), 16 * p + 7);  // pattern id, read on a hit only
             e.y = tr.id;
             wave_edge[pos] = e;
             wave_dist[pos] = (uint8_t)__popc(fZ);

@@ -36,7 +36,7 @@ struct DevBuf {
 
 // Pair-kernel schedule.
 struct Sched {
-  uint32_t texts_per_item = 4096;
+  uint32_t texts_per_item = 16384;
   uint32_t waves_per_simd = 8;
   bool peq_lds = false;
 };

@@ -138,6 +138,7 @@ struct tcrnet_index {
   int device = 0;
   int k_index = 1;
   std::atomic<uint32_t> n_total{0};
+  uint64_t n_promised = 0;  // resident sequences once every accepted insert is in (under mu)
   uint32_t deg_cap = 0;
   DevBuf deg;
   std::vector<SegPtr> segs;
@@ -174,6 +175,7 @@ int32_t check_k(int32_t k) {
 int32_t check_request_seqs(const tcrnet_seqs* s) {
   if (!s) return set_error(TCRNET_EINVAL, "NULL sequence set");
   if (s->n && (!s->offsets || !s->data)) return set_error(TCRNET_EINVAL, "NULL data or offsets");
+  if (s->n > TCRNET_MAX_SEQS) return set_error(TCRNET_EINVAL, "more than 2^28 sequences");
   static const char kAlpha[] = "ARNDCQEGHILKMFPSTWYV";
   bool ok[256] = {false};
   for (const char* a = kAlpha; *a; ++a) ok[(unsigned char)*a] = true;
@@ -596,6 +598,7 @@ int32_t tcrnet_index_create(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k_
   if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return hip_error(e, "index build");
   idx->segs.push_back(base);
   idx->n_total = n;
+  idx->n_promised = n;
   // serving schedule and budget
   idx->sched = pick_sched(ctx, n, k_index);
   // requests are small next to the resident set: short work items keep many
@@ -693,6 +696,14 @@ int32_t tcrnet_submit(tcrnet_index* idx, const tcrnet_seqs* q, int32_t k, int32_
   if (idx->stop) {
     delete r;
     return set_error(TCRNET_ESTATE, "index is shutting down");
+  }
+  if (r->insert) {
+    // every accepted insert will be resident: keep the total in range
+    if ((uint64_t)idx->n_promised + r->m > TCRNET_MAX_SEQS) {
+      delete r;
+      return set_error(TCRNET_EINVAL, "insert would grow the index past 2^28 sequences");
+    }
+    idx->n_promised += r->m;
   }
   r->ticket = idx->next_ticket++;
   idx->reqs[r->ticket] = r;
