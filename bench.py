@@ -23,6 +23,7 @@ Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 2]
 from __future__ import annotations
 
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -49,6 +50,36 @@ def log(msg: str):
 def load_model(name: str) -> dict:
     with open(os.path.join(ROOT, "bench_model.json")) as f:
         return json.load(f)["workloads"][name]
+
+
+def source_sha1(files) -> str:
+    h = hashlib.sha1()
+    for rel in files:
+        with open(os.path.join(ROOT, rel), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def counted_traffic(texts_per_item: int):
+    """HBM bytes per pair-kernel launch from the committed FETCH_SIZE /
+    WRITE_SIZE counts (bench_traffic.json), each scaled by what the same
+    counter reads for a device copy of known size; None once the kernel's
+    sources or the work-item size differ from those the counters were taken
+    with."""
+    path = os.path.join(ROOT, "bench_traffic.json")
+    if not os.path.exists(path):
+        log("no HBM counter record: traffic not reported")
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if source_sha1(rec["sources"]) != rec["sources_sha1"]:
+        log("pair kernel sources changed since the HBM counters were taken: traffic not reported")
+        return None
+    if texts_per_item != rec["texts_per_item"]:
+        log(f"HBM counters were taken at {rec['texts_per_item']} texts per item: traffic not reported")
+        return None
+    kib = 1024.0
+    return (rec["fetch_kib"] * kib * rec["fetch_scale"] + rec["write_kib"] * kib * rec["write_scale"])
 
 
 def evaluated_pairs(lengths: np.ndarray, k: int) -> int:
@@ -90,12 +121,17 @@ def cpu_baseline(seqs, k, target_s: float) -> dict:
 
     o = oracle.Oracle()
     n = seqs.n
-    # first a short probe to size the sample, then the timed sample
-    rows = 8
-    t0 = time.perf_counter()
-    o.build(seqs, k, row_lo=0, row_hi=rows)
-    probe = time.perf_counter() - t0
-    rows = max(rows, min(n, int(rows * target_s / max(probe, 1e-3))))
+    # probes of doubling size (at least a second of work, so that every
+    # thread is busy) to size the sample, then the timed sample
+    rows = 2 * o.threads()
+    while True:
+        t0 = time.perf_counter()
+        o.build(seqs, k, row_lo=0, row_hi=rows)
+        probe = time.perf_counter() - t0
+        if probe >= 1.0 or rows >= n:
+            break
+        rows = min(n, 2 * rows)
+    rows = max(1, min(n, int(rows * target_s / max(probe, 1e-3))))
     t0 = time.perf_counter()
     o.build(seqs, k, row_lo=0, row_hi=rows)
     dt = time.perf_counter() - t0
@@ -309,7 +345,8 @@ def main():
             "peak": PEAK_LANE_OPS / 1e12,
             "unit": "T lane-instr/s",
             "frac": achieved / PEAK_LANE_OPS if T_used == trav["texts_per_item"] else None,
-            "traffic": None,
+            "traffic": counted_traffic(T_used),
+            "traffic_unit": "B per launch",
             "kernel": "k_pairs",
             "work_per_unit": f"{WAVE} lanes x {T_STEP_INSTR} VALU instr per wave text step",
             "units_per_launch": trav["wave_steps"],

@@ -111,6 +111,7 @@ int32_t run_pipeline(tcrnet_ctx* ctx, Pipeline& pl, PipeParams pp, hipStream_t s
     inf.build_ms += bt;
     inf.pair_launches += 1;
     inf.evaluated_pairs = m.plan.evaluated_pairs;
+    if (m.cnt.fault) return set_error(TCRNET_EDEVICE, "device sort stalled (internal)");
     if (m.cnt.err != kNoError) return set_error(TCRNET_EINVAL, "%s", input_error_message(m.cnt.err).c_str());
     if (m.plan.pad) return set_error(TCRNET_EDEVICE, "work plan overflow (internal)");
     *E = m.cnt.edges;
@@ -416,6 +417,7 @@ int32_t tcrnet_build_batch(tcrnet_ctx* ctx, const tcrnet_seqs* reps, uint32_t n_
       info.build_ms += bt;
       info.pair_launches += 1;
       info.evaluated_pairs = m.plan.evaluated_pairs;
+      if (m.cnt.fault) return set_error(TCRNET_EDEVICE, "device sort stalled (internal)");
       if (m.cnt.err != kNoError) {
         const unsigned long long idx = m.cnt.err >> 2;
         const uint32_t r = (uint32_t)(std::upper_bound(seg.begin(), seg.end(), (uint32_t)idx) - seg.begin()) - 1;

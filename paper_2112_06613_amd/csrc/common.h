@@ -114,7 +114,8 @@ struct alignas(256) Counters {
   unsigned long long err;         // min over bad inputs of (index << 2 | code),
                                   // code 1: residue outside the alphabet,
                                   // code 2: length 0 or > 32; ~0: none
-  unsigned long long pad1[14];
+  unsigned long long fault;       // nonzero: a device sort pass stalled
+  unsigned long long pad1[13];
 };
 constexpr unsigned long long kNoError = ~0ull;
 

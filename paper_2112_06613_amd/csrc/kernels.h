@@ -32,14 +32,16 @@ void launch_encode(const char* d_data, const uint64_t* d_off, uint32_t n, const 
                    uint64_t* key, uint32_t* val, Counters* cnt, hipStream_t st);
 
 // Stable LSD radix sort of (key, val) pairs by key bits [0, key_bits), 8 bits a
-// pass.  Buffers are ping-ponged; returns true if the result ended in the
-// *_alt buffers.  val may be NULL (keys only).  tmp must hold
-// radix_tmp_words(n) words.  The element count is min(n, *d_n) when d_n is
-// not NULL (read on the device, so the launch sequence needs no host sync);
-// grids are sized for n.
+// pass, one kernel per pass after a counting kernel.  Buffers are
+// ping-ponged; returns true if the result ended in the *_alt buffers.  val may
+// be NULL (keys only).  tmp must hold radix_tmp_words(n) words (8-byte
+// aligned).  The element count is min(n, *d_n) when d_n is not NULL (read on
+// the device, so the launch sequence needs no host sync); grids are sized for
+// n.  *fault is set to nonzero if a pass stalls (an internal error).
 uint64_t radix_tmp_words(uint64_t n);
 bool radix_sort(uint64_t* key, uint64_t* key_alt, uint32_t* val, uint32_t* val_alt, uint64_t n,
-                const unsigned long long* d_n, int key_bits, uint32_t* tmp, hipStream_t st);
+                const unsigned long long* d_n, int key_bits, uint32_t* tmp, unsigned long long* fault,
+                hipStream_t st);
 
 // Step a2: bucket boundaries.  key holds sorted keys; combo = key >> combo_shift
 // is (segment * 33 + length).  off[c] = first sorted position whose combo >= c,

@@ -93,7 +93,7 @@ void stage_prepare(Pipeline& pl, const char* d_data, const uint64_t* d_off, uint
                 pl.key.as<uint64_t>(), pl.val.as<uint32_t>(), pl.cnt(), st);
   const bool alt = radix_sort(pl.key.as<uint64_t>(), pl.key2.as<uint64_t>(), pl.val.as<uint32_t>(),
                               pl.val2.as<uint32_t>(), n, nullptr, encode_key_bits(seg_bits), pl.tmp.as<uint32_t>(),
-                              st);
+                              &pl.cnt()->fault, st);
   const uint64_t* skey = alt ? pl.key2.as<uint64_t>() : pl.key.as<uint64_t>();
   const uint32_t* sval = alt ? pl.val2.as<uint32_t>() : pl.val.as<uint32_t>();
   launch_bucket_bounds(skey, n, encode_combo_shift(seg_bits), n_combo, off, st);
@@ -110,7 +110,8 @@ void stage_prepare_records(Pipeline& pl, const SeqRec* rec, uint32_t n, const Se
   }
   launch_record_keys(rec, n, pl.key.as<uint64_t>(), pl.val.as<uint32_t>(), st);
   const bool alt = radix_sort(pl.key.as<uint64_t>(), pl.key2.as<uint64_t>(), pl.val.as<uint32_t>(),
-                              pl.val2.as<uint32_t>(), n, nullptr, encode_key_bits(0), pl.tmp.as<uint32_t>(), st);
+                              pl.val2.as<uint32_t>(), n, nullptr, encode_key_bits(0), pl.tmp.as<uint32_t>(),
+                              &pl.cnt()->fault, st);
   const uint64_t* skey = alt ? pl.key2.as<uint64_t>() : pl.key.as<uint64_t>();
   const uint32_t* sval = alt ? pl.val2.as<uint32_t>() : pl.val.as<uint32_t>();
   launch_bucket_bounds(skey, n, encode_combo_shift(0), 64, off, st);
@@ -145,7 +146,7 @@ void stage_canon(Pipeline& pl, int mode, int shift, uint64_t capacity, uint32_t*
   launch_edge_keys(pl.edges.as<uint32_t>(), d_dist ? pl.edist.as<uint8_t>() : nullptr, capacity, &cnt->edges, mode,
                    shift, pl.ekeys.as<uint64_t>(), st);
   const bool ealt = radix_sort(pl.ekeys.as<uint64_t>(), pl.ekeys2.as<uint64_t>(), nullptr, nullptr, capacity,
-                               &cnt->edges, 2 * shift + (d_dist ? 5 : 0), pl.tmp.as<uint32_t>(), st);
+                               &cnt->edges, 2 * shift + (d_dist ? 5 : 0), pl.tmp.as<uint32_t>(), &cnt->fault, st);
   const uint64_t* sk = ealt ? pl.ekeys2.as<uint64_t>() : pl.ekeys.as<uint64_t>();
   launch_unpack(sk, capacity, &cnt->edges, mode, shift, d_pairs, d_deg, d_dist, st);
 }

@@ -30,6 +30,7 @@ __global__ void k_reset_counters(Counters* c) {
   if (threadIdx.x == 0) {
     c->edges = 0;
     c->err = kNoError;
+    c->fault = 0;
   }
 }
 

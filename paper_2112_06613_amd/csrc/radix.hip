@@ -1,17 +1,38 @@
 // Stable LSD radix sort of 64-bit keys (with optional 32-bit values), 8 bits
-// per pass: per-block digit histograms, one exclusive scan over
-// (digit, block), and a stable scatter that ranks equal digits inside each
-// wave with ballots.
+// per pass, one kernel per pass.
+//
+// A counting kernel reads every key once and forms the digit histograms of
+// all passes.  Each pass kernel then takes tiles in launch order from an
+// atomic ticket, ranks its keys by digit (wave ballots, stable), publishes
+// the tile's per-digit counts, and adds up the counts of all earlier tiles by
+// decoupled look-back (Merrill & Garland, "Single-pass parallel prefix scan
+// with decoupled look-back", 2016; its use for radix sorting is the
+// "Onesweep" sort of Adinets & Merrill, 2022).  Keys are staged in LDS in
+// digit order, so each digit's run of a tile leaves with consecutive stores.
+//
+// Forward progress: a tile only waits for tiles with smaller tickets, which
+// were taken by blocks already running; tile 0 waits for nothing.  A tile
+// whose first key lies past the element count takes no part (neither
+// publishes nor waits), and every tile before it publishes.  The wait is
+// bounded all the same: a stall past the bound sets *fault and ends the
+// look-back (the output is then wrong but stays in bounds).
 #include "kernels.h"
 
 namespace tcr {
 
 namespace {
 
-constexpr int kRB = 256;                 // threads per block
-constexpr int kRItems = 16;              // keys per thread per tile
-constexpr int kRTile = kRB * kRItems;    // keys per block
-constexpr int kScanThreads = 1024;
+constexpr int kRB = 256;                    // threads per block
+constexpr int kRWaves = kRB / 64;
+constexpr int kRRounds = 8;                 // rounds of 64 keys per wave
+constexpr int kRWaveKeys = 64 * kRRounds;   // consecutive keys of one wave
+constexpr int kRTile = kRB * kRRounds;      // keys per tile
+constexpr int kMaxPasses = 8;               // 64-bit keys
+constexpr int kTicketWords = 32;            // one ticket per pass, padded
+constexpr uint64_t kFlagAgg = 1ull << 62;   // status: the tile's own count
+constexpr uint64_t kFlagPre = 1ull << 63;   // status: count through this tile
+constexpr uint64_t kValMask = kFlagAgg - 1;
+constexpr uint32_t kSpinLimit = 1u << 22;
 
 __device__ __forceinline__ uint64_t eff_n(uint64_t n, const unsigned long long* dn) {
   if (!dn) return n;
@@ -19,123 +40,89 @@ __device__ __forceinline__ uint64_t eff_n(uint64_t n, const unsigned long long* 
   return v < n ? v : n;
 }
 
-__global__ __launch_bounds__(kRB) void k_radix_hist(const uint64_t* __restrict__ key, uint64_t n_max,
+__device__ __forceinline__ uint64_t status_load(const unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+__device__ __forceinline__ void status_store(unsigned long long* p, uint64_t v) {
+  __hip_atomic_store(p, (unsigned long long)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Histograms and tickets start at zero.
+__global__ __launch_bounds__(kRB) void k_radix_clear(unsigned long long* __restrict__ p, uint32_t words) {
+  for (uint32_t i = threadIdx.x; i < words; i += kRB) p[i] = 0;
+}
+
+// Digit counts of every pass; also clears this tile's look-back status words.
+__global__ __launch_bounds__(kRB) void k_radix_count(const uint64_t* __restrict__ key, uint64_t n_max,
+                                                     const unsigned long long* __restrict__ dn, int passes,
+                                                     unsigned long long* __restrict__ hist,
+                                                     unsigned long long* __restrict__ status, uint64_t nb) {
+  __shared__ uint32_t h[kMaxPasses][256];
+  const uint32_t tid = threadIdx.x;
+  const uint64_t n = eff_n(n_max, dn);
+#pragma unroll
+  for (int p = 0; p < kMaxPasses; ++p) h[p][tid] = 0;
+  for (int p = 0; p < passes; ++p) status[((uint64_t)p * nb + blockIdx.x) * 256 + tid] = 0;
+  __syncthreads();
+  const uint64_t base = (uint64_t)blockIdx.x * kRTile;
+  for (int i = tid; i < kRTile; i += kRB) {
+    const uint64_t idx = base + i;
+    if (idx < n) {
+      const uint64_t kv = key[idx];
+      for (int p = 0; p < passes; ++p) atomicAdd(&h[p][(kv >> (8 * p)) & 255u], 1u);
+    }
+  }
+  __syncthreads();
+  for (int p = 0; p < passes; ++p)
+    if (h[p][tid]) atomicAdd(&hist[p * 256 + tid], (unsigned long long)h[p][tid]);
+}
+
+// One pass over digit (key >> shift) & 255.  hist: this pass's global digit
+// counts; ticket: this pass's tile counter; status: this pass's look-back
+// words, 256 per tile.
+template <bool kVal>
+__global__ __launch_bounds__(kRB) void k_radix_pass(const uint64_t* __restrict__ key,
+                                                    const uint32_t* __restrict__ val, uint64_t* __restrict__ okey,
+                                                    uint32_t* __restrict__ oval, uint64_t n_max,
                                                     const unsigned long long* __restrict__ dn, int shift,
-                                                    uint32_t* __restrict__ hist, uint32_t nblocks) {
-  __shared__ uint32_t h[256];
+                                                    const unsigned long long* __restrict__ hist,
+                                                    unsigned long long* __restrict__ ticket,
+                                                    unsigned long long* __restrict__ status,
+                                                    unsigned long long* __restrict__ fault) {
+  __shared__ uint64_t s_key[kRTile];
+  __shared__ uint32_t s_val[kVal ? kRTile : 1];
+  __shared__ uint32_t s_wc[kRWaves][256];   // per wave and digit: running count, then offset
+  __shared__ uint64_t s_scan_g[256];
+  __shared__ uint32_t s_scan_t[256];
+  __shared__ uint64_t s_out[256];           // output index of a digit's run = s_out[d] + tile position
+  __shared__ uint32_t s_texcl[256];         // tile position of a digit's run
+  __shared__ uint32_t s_id;
+  const uint32_t tid = threadIdx.x;
+  const uint32_t lane = tid & 63u;
+  const uint32_t wid = tid >> 6;
   const uint64_t n = eff_n(n_max, dn);
-  h[threadIdx.x] = 0;
-  __syncthreads();
-  const uint64_t base = (uint64_t)blockIdx.x * kRTile;
-  for (int i = threadIdx.x; i < kRTile; i += kRB) {
-    const uint64_t idx = base + i;
-    if (idx < n) atomicAdd(&h[(key[idx] >> shift) & 255u], 1u);
-  }
-  __syncthreads();
-  hist[(uint64_t)threadIdx.x * nblocks + blockIdx.x] = h[threadIdx.x];
-}
-
-// Exclusive scan of `total` counts in place, one block.
-__global__ __launch_bounds__(kScanThreads) void k_radix_scan(uint32_t* __restrict__ hist, uint64_t total) {
-  __shared__ uint32_t sums[kScanThreads];
-  const uint64_t per = (total + kScanThreads - 1) / kScanThreads;
-  const uint64_t lo = per * threadIdx.x;
-  const uint64_t hi = lo + per < total ? lo + per : total;
-  uint32_t s = 0;
-  for (uint64_t i = lo; i < hi; ++i) s += hist[i];
-  sums[threadIdx.x] = s;
-  __syncthreads();
-  for (int d = 1; d < kScanThreads; d <<= 1) {
-    uint32_t x = threadIdx.x >= (unsigned)d ? sums[threadIdx.x - d] : 0;
-    __syncthreads();
-    sums[threadIdx.x] += x;
-    __syncthreads();
-  }
-  uint32_t run = sums[threadIdx.x] - s;
-  for (uint64_t i = lo; i < hi; ++i) {
-    const uint32_t v = hist[i];
-    hist[i] = run;
-    run += v;
-  }
-}
-
-// Large scans in three passes: chunk sums, a scan of the sums, then each
-// chunk rescanned from its offset.  kScanChunk entries per block.
-constexpr int kScanChunk = 4096;
-
-__device__ uint32_t block_excl_scan_u32(uint32_t v, uint32_t* sh, uint32_t& total) {
-  const int t = threadIdx.x;
-  sh[t] = v;
-  __syncthreads();
-  for (int d = 1; d < kRB; d <<= 1) {
-    const uint32_t x = t >= d ? sh[t - d] : 0;
-    __syncthreads();
-    sh[t] += x;
-    __syncthreads();
-  }
-  total = sh[kRB - 1];
-  const uint32_t r = sh[t] - v;
-  __syncthreads();
-  return r;
-}
-
-__global__ __launch_bounds__(kRB) void k_scan_partials(const uint32_t* __restrict__ a, uint64_t total,
-                                                       uint32_t* __restrict__ partial) {
-  __shared__ uint32_t sh[kRB];
-  const uint64_t base = (uint64_t)blockIdx.x * kScanChunk;
-  uint32_t s = 0;
-  for (int i = threadIdx.x; i < kScanChunk; i += kRB) {
-    const uint64_t idx = base + i;
-    if (idx < total) s += a[idx];
-  }
-  uint32_t tot;
-  block_excl_scan_u32(s, sh, tot);
-  if (threadIdx.x == 0) partial[blockIdx.x] = tot;
-}
-
-__global__ __launch_bounds__(kRB) void k_scan_chunks(uint32_t* __restrict__ a, uint64_t total,
-                                                     const uint32_t* __restrict__ partial_excl) {
-  __shared__ uint32_t sh[kRB];
-  const uint64_t base = (uint64_t)blockIdx.x * kScanChunk;
-  // each thread owns kScanChunk / kRB consecutive entries
-  constexpr int per = kScanChunk / kRB;
-  const uint64_t lo = base + (uint64_t)threadIdx.x * per;
-  uint32_t v[per];
-  uint32_t s = 0;
+  if (tid == 0) s_id = (uint32_t)atomicAdd(ticket, 1ull);
 #pragma unroll
-  for (int i = 0; i < per; ++i) {
-    v[i] = lo + i < total ? a[lo + i] : 0u;
-    s += v[i];
-  }
-  uint32_t tot;
-  uint32_t run = partial_excl[blockIdx.x] + block_excl_scan_u32(s, sh, tot);
-#pragma unroll
-  for (int i = 0; i < per; ++i) {
-    if (lo + i < total) a[lo + i] = run;
-    run += v[i];
-  }
-}
+  for (int w = 0; w < kRWaves; ++w) s_wc[w][tid] = 0;
+  __syncthreads();
+  const uint32_t id = s_id;
+  const uint64_t base = (uint64_t)id * kRTile;
+  if (base >= n) return;  // block-uniform: this tile is past the end
 
-__global__ __launch_bounds__(kRB) void k_radix_scatter(const uint64_t* __restrict__ key,
-                                                       const uint32_t* __restrict__ val,
-                                                       uint64_t* __restrict__ okey, uint32_t* __restrict__ oval,
-                                                       uint64_t n_max, const unsigned long long* __restrict__ dn,
-                                                       int shift, const uint32_t* __restrict__ offs,
-                                                       uint32_t nblocks) {
-  __shared__ uint32_t run[256];
-  const uint64_t n = eff_n(n_max, dn);
-  __shared__ uint32_t wcnt[kRB / 64][256];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wid = tid >> 6;
-  run[tid] = offs[(uint64_t)tid * nblocks + blockIdx.x];
-  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  const uint64_t base = (uint64_t)blockIdx.x * kRTile;
-  for (int it = 0; it < kRItems; ++it) {
-    const uint64_t idx = base + (uint64_t)it * kRB + tid;
+  // 1. stable ranks inside each wave's run of keys
+  const uint64_t lt_mask = lane == 0 ? 0ull : (~0ull >> (64 - lane));
+  const uint64_t wbase = base + (uint64_t)wid * kRWaveKeys;
+  uint64_t kv[kRRounds];
+  uint32_t vv[kRRounds];
+  uint32_t rk[kRRounds];
+#pragma unroll
+  for (int r = 0; r < kRRounds; ++r) {
+    const uint64_t idx = wbase + (uint64_t)r * 64 + lane;
     const bool ok = idx < n;
-    const uint64_t kv = ok ? key[idx] : 0;
-    const uint32_t d = (uint32_t)(kv >> shift) & 255u;
+    kv[r] = ok ? key[idx] : 0ull;
+    vv[r] = (kVal && ok) ? val[idx] : 0u;
+    const uint32_t d = (uint32_t)(kv[r] >> shift) & 255u;
     uint64_t peers = __ballot(ok);
 #pragma unroll
     for (int b = 0; b < 8; ++b) {
@@ -143,29 +130,84 @@ __global__ __launch_bounds__(kRB) void k_radix_scatter(const uint64_t* __restric
       const uint64_t bb = __ballot(bit);
       peers &= bit ? bb : ~bb;
     }
-    const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+    const uint32_t before = ok ? s_wc[wid][d] : 0u;
+    rk[r] = before + (uint32_t)__popcll(peers & lt_mask);
+    if (ok && (peers & lt_mask) == 0ull) s_wc[wid][d] = before + (uint32_t)__popcll(peers);
+    __builtin_amdgcn_wave_barrier();
+  }
+  __syncthreads();
+
+  // 2. thread d: wave offsets of digit d, the tile's count, publish it
+  const uint32_t d = tid;
+  uint32_t cnt = 0;
 #pragma unroll
-    for (int w = 0; w < kRB / 64; ++w) wcnt[w][tid] = 0;
+  for (int w = 0; w < kRWaves; ++w) {
+    const uint32_t c = s_wc[w][d];
+    s_wc[w][d] = cnt;
+    cnt += c;
+  }
+  unsigned long long* my_status = status + (uint64_t)id * 256 + d;
+  status_store(my_status, (id == 0 ? kFlagPre : kFlagAgg) | cnt);
+
+  // 3. exclusive scans over digits: tile positions and global offsets
+  s_scan_t[d] = cnt;
+  s_scan_g[d] = hist[d];
+  __syncthreads();
+  for (int s = 1; s < 256; s <<= 1) {
+    const uint32_t xt = d >= (uint32_t)s ? s_scan_t[d - s] : 0u;
+    const uint64_t xg = d >= (uint32_t)s ? s_scan_g[d - s] : 0ull;
     __syncthreads();
-    if (ok && rank == 0) wcnt[wid][d] = (uint32_t)__popcll(peers);
+    s_scan_t[d] += xt;
+    s_scan_g[d] += xg;
     __syncthreads();
-    {
-      uint32_t r = run[tid];
-#pragma unroll
-      for (int w = 0; w < kRB / 64; ++w) {
-        const uint32_t c = wcnt[w][tid];
-        wcnt[w][tid] = r;
-        r += c;
+  }
+  const uint32_t texcl = s_scan_t[d] - cnt;
+  const uint64_t gexcl = s_scan_g[d] - hist[d];
+
+  // 4. look-back: keys of digit d in all earlier tiles
+  uint64_t prefix = 0;
+  if (id > 0) {
+    uint32_t spins = 0;
+    for (uint32_t j = id; j > 0;) {
+      --j;
+      uint64_t v;
+      for (;;) {
+        v = status_load(status + (uint64_t)j * 256 + d);
+        if (v & (kFlagAgg | kFlagPre)) break;
+        if (++spins >= kSpinLimit) {
+          atomicOr(fault, 1ull);
+          v = kFlagPre;
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
       }
-      run[tid] = r;
+      prefix += v & kValMask;
+      if (v & kFlagPre) break;
     }
-    __syncthreads();
-    if (ok) {
-      const uint32_t pos = wcnt[wid][d] + rank;
-      okey[pos] = kv;
-      if (val) oval[pos] = val[idx];
+    status_store(my_status, kFlagPre | (prefix + cnt));
+  }
+  s_texcl[d] = texcl;
+  s_out[d] = gexcl + prefix - texcl;
+  __syncthreads();
+
+  // 5. stage the tile in digit order, then write each digit's run
+#pragma unroll
+  for (int r = 0; r < kRRounds; ++r) {
+    const uint64_t idx = wbase + (uint64_t)r * 64 + lane;
+    if (idx < n) {
+      const uint32_t dr = (uint32_t)(kv[r] >> shift) & 255u;
+      const uint32_t pos = s_texcl[dr] + s_wc[wid][dr] + rk[r];
+      s_key[pos] = kv[r];
+      if (kVal) s_val[pos] = vv[r];
     }
-    __syncthreads();
+  }
+  __syncthreads();
+  const uint32_t tn = n - base < (uint64_t)kRTile ? (uint32_t)(n - base) : (uint32_t)kRTile;
+  for (uint32_t i = tid; i < tn; i += kRB) {
+    const uint64_t k = s_key[i];
+    const uint64_t o = s_out[(uint32_t)(k >> shift) & 255u] + i;
+    okey[o] = k;
+    if (kVal) oval[o] = s_val[i];
   }
 }
 
@@ -173,36 +215,32 @@ __global__ __launch_bounds__(kRB) void k_radix_scatter(const uint64_t* __restric
 
 uint64_t radix_tmp_words(uint64_t n) {
   const uint64_t nb = (n + kRTile - 1) / kRTile;
-  const uint64_t hist = 256 * (nb ? nb : 1);
-  return hist + (hist + kScanChunk - 1) / kScanChunk + 1;  // histogram + chunk sums
-}
-
-// Exclusive scan of `total` words in place (partial: scratch of
-// ceil(total / kScanChunk) words).
-static void scan_u32(uint32_t* a, uint64_t total, uint32_t* partial, hipStream_t st) {
-  const uint64_t chunks = (total + kScanChunk - 1) / kScanChunk;
-  if (chunks <= 8) {
-    hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(kScanThreads), 0, st, a, total);
-    return;
-  }
-  hipLaunchKernelGGL(k_scan_partials, dim3((uint32_t)chunks), dim3(kRB), 0, st, a, total, partial);
-  hipLaunchKernelGGL(k_radix_scan, dim3(1), dim3(kScanThreads), 0, st, partial, chunks);
-  hipLaunchKernelGGL(k_scan_chunks, dim3((uint32_t)chunks), dim3(kRB), 0, st, a, total, partial);
+  return 2 * ((uint64_t)kMaxPasses * 256 + kTicketWords + (uint64_t)kMaxPasses * (nb ? nb : 1) * 256);
 }
 
 bool radix_sort(uint64_t* key, uint64_t* key_alt, uint32_t* val, uint32_t* val_alt, uint64_t n,
-                const unsigned long long* d_n, int key_bits, uint32_t* tmp, hipStream_t st) {
+                const unsigned long long* d_n, int key_bits, uint32_t* tmp, unsigned long long* fault,
+                hipStream_t st) {
   if (n <= 1 || key_bits <= 0) return false;
-  const uint32_t nb = (uint32_t)((n + kRTile - 1) / kRTile);
+  const int passes = key_bits > 8 * kMaxPasses ? kMaxPasses : (key_bits + 7) / 8;
+  const uint64_t nb = (n + kRTile - 1) / kRTile;
+  unsigned long long* hist = reinterpret_cast<unsigned long long*>(tmp);
+  unsigned long long* ticket = hist + kMaxPasses * 256;
+  unsigned long long* status = ticket + kTicketWords;
+  hipLaunchKernelGGL(k_radix_clear, dim3(1), dim3(kRB), 0, st, hist, (uint32_t)(kMaxPasses * 256 + kTicketWords));
+  hipLaunchKernelGGL(k_radix_count, dim3((uint32_t)nb), dim3(kRB), 0, st, key, n, d_n, passes, hist, status, nb);
   bool alt = false;
-  for (int shift = 0; shift < key_bits; shift += 8) {
+  for (int p = 0; p < passes; ++p) {
     const uint64_t* ki = alt ? key_alt : key;
     uint64_t* ko = alt ? key : key_alt;
-    const uint32_t* vi = val ? (alt ? val_alt : val) : nullptr;
-    uint32_t* vo = val ? (alt ? val : val_alt) : nullptr;
-    hipLaunchKernelGGL(k_radix_hist, dim3(nb), dim3(kRB), 0, st, ki, n, d_n, shift, tmp, nb);
-    scan_u32(tmp, (uint64_t)256 * nb, tmp + (uint64_t)256 * nb, st);
-    hipLaunchKernelGGL(k_radix_scatter, dim3(nb), dim3(kRB), 0, st, ki, vi, ko, vo, n, d_n, shift, tmp, nb);
+    unsigned long long* sp = status + (uint64_t)p * nb * 256;
+    if (val) {
+      hipLaunchKernelGGL(k_radix_pass<true>, dim3((uint32_t)nb), dim3(kRB), 0, st, ki, alt ? val_alt : val,
+                         ko, alt ? val : val_alt, n, d_n, 8 * p, hist + p * 256, ticket + p, sp, fault);
+    } else {
+      hipLaunchKernelGGL(k_radix_pass<false>, dim3((uint32_t)nb), dim3(kRB), 0, st, ki, nullptr, ko, nullptr, n,
+                         d_n, 8 * p, hist + p * 256, ticket + p, sp, fault);
+    }
     alt = !alt;
   }
   return alt;

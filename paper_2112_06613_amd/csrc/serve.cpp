@@ -388,6 +388,10 @@ hipError_t merge_segments(tcrnet_index* idx) {
 void on_meta(tcrnet_index* idx, Slot* s) {
   Request* r = s->req;
   const Meta m = *s->h_meta.as<Meta>();
+  if (m.cnt.fault) {
+    fail_request(idx, s, r, TCRNET_EDEVICE, "device sort stalled (internal)");
+    return;
+  }
   if (m.cnt.err != kNoError) {
     fail_request(idx, s, r, TCRNET_EINVAL, input_error_message(m.cnt.err));
     return;
