@@ -121,20 +121,20 @@ def cpu_baseline(seqs, k, target_s: float) -> dict:
 
     o = oracle.Oracle()
     n = seqs.n
-    # probes of doubling size (at least a second of work, so that every
-    # thread is busy) to size the sample, then the timed sample
-    rows = 2 * o.threads()
-    while True:
-        t0 = time.perf_counter()
-        o.build(seqs, k, row_lo=0, row_hi=rows)
-        probe = time.perf_counter() - t0
-        if probe >= 1.0 or rows >= n:
-            break
-        rows = min(n, 2 * rows)
-    rows = max(1, min(n, int(rows * target_s / max(probe, 1e-3))))
+    # the oracle hands rows to its threads in chunks of 16 (OpenMP dynamic
+    # schedule), so the sample is a whole number of chunks per thread: one
+    # round first, then as many rounds as fit the target time
+    chunk = 16 * o.threads()
+    rows = min(n, chunk)
     t0 = time.perf_counter()
     o.build(seqs, k, row_lo=0, row_hi=rows)
     dt = time.perf_counter() - t0
+    rounds = max(1, int(round(target_s / max(dt, 1e-3))))
+    if rounds > 1 and rows < n:
+        rows = min(n, chunk * rounds)
+        t0 = time.perf_counter()
+        o.build(seqs, k, row_lo=0, row_hi=rows)
+        dt = time.perf_counter() - t0
     pairs = sum(n - 1 - i for i in range(rows))
     return {"value": pairs / dt, "unit": "pairs/s", "cores": o.threads(), "kind": "oracle",
             "sample": f"rows 0..{rows - 1} of the N={n} k={k} workload against all later rows "

@@ -34,14 +34,7 @@ struct alignas(64) SeqRec {
   uint32_t nxt[kSkipDepths];
 };
 
-// The first half of a SeqRec (codes, length, id): what the pair kernel reads
-// of a text up front.
-struct alignas(32) SeqHead {
-  uint32_t w[6];
-  uint32_t len;
-  uint32_t id;
-};
-static_assert(sizeof(SeqRec) == 2 * sizeof(SeqHead), "SeqRec = head + group ends");
+static_assert(sizeof(SeqRec) == 64, "one record = one 64-byte line");
 
 // Bit masks of one pattern: eq[c] has bit q set iff residue q has code c
 // (Myers' Peq table).  80 bytes.

@@ -54,15 +54,18 @@ __device__ __forceinline__ uint32_t low_mask(uint32_t r) { return r >= 32 ? ~0u 
 // text records are read-only for the whole launch, so they are read through
 // the constant address space (scalar loads into SGPRs); pattern data through
 // the global one.  (The host compilation pass only parses kernel bodies.)
+// load_const_at reads at a 32-bit byte offset from a wave-uniform base (the
+// offset stays a scalar register operand of the load: no 64-bit address
+// arithmetic per text).
 template <class T>
-__device__ __forceinline__ T load_const(const T* p, uint32_t i) {
+__device__ __forceinline__ T load_const_at(const void* base, uint32_t byte_off) {
 #if defined(__HIP_DEVICE_COMPILE__)
-  const __attribute__((address_space(4))) T* q = (const __attribute__((address_space(4))) T*)p;
+  const __attribute__((address_space(4))) char* q = (const __attribute__((address_space(4))) char*)base;
   T v;
-  __builtin_memcpy(&v, (const T*)(q + i), sizeof(T));
+  __builtin_memcpy(&v, (const T*)(q + byte_off), sizeof(T));
   return v;
 #else
-  return p[i];
+  return *(const T*)((const char*)base + byte_off);
 #endif
 }
 
@@ -198,9 +201,14 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     // diagonal cell D[delta+j][j] after j steps and D[m][n] = lev at the end.
     // A lane outside the item starts at ~0 (never within k).
     const uint32_t z_item = lane_ok ? (1u << delta) - 1u : ~0u;
-    uint32_t tb = d.t0 + c * T;
-    const uint32_t te = min(d.t0 + d.nt, tb + T);
+    const uint32_t tb0 = d.t0 + c * T;
+    const uint32_t te = min(d.t0 + d.nt, tb0 + T);
+    uint32_t tb = tb0;
     if (d.tri && tb < gbase + 1) tb = gbase + 1;
+    // in a triangle item, texts before tri_end still have patterns at or
+    // after them in the wave (those lanes are masked off)
+    const uint32_t tri_end = d.tri ? gbase + kWave : 0u;
+    const SeqRec* tbase = trec + tb0;  // this item's text records
 
     // Register stack of the state after each of the first kDepth text steps.
     // Texts are visited in sorted order, so a text sharing its first r
@@ -212,17 +220,21 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     uint32_t sVP[kDepth], sVN[kDepth], sZ[kDepth];
     uint32_t r = 0;
 
-    const uint32_t* tnxt = reinterpret_cast<const uint32_t*>(trec) + 8;  // nxt[] of record 0
     uint32_t t = tb;
     while (t < te) {
-      const SeqHead tr = load_const(reinterpret_cast<const SeqHead*>(trec), 2 * t);
+      // the whole record (codes, length, id, group ends): one scalar load
+      const SeqRec tr = load_const_at<SeqRec>(tbase, (t - tb0) * (uint32_t)sizeof(SeqRec));
       uint32_t tn = t + 1;  // next text
+      // common prefix of this text with the next visited one (from the
+      // record's packed lengths): the steps the next text can reuse
+      uint32_t lcp_next = 0;
       uint32_t z_text = z_item;
-      bool can_skip = true;
-      if (d.tri && t - gbase < 64u) {
-        if (lane >= t - gbase) z_text = ~0u;  // pattern not before the text
-        can_skip = false;                     // the next texts add valid lanes
-      }
+      // ragged: the set of valid lanes still grows with the next texts, so
+      // neither jumps (tcap keeps them at the next text) nor resumed state
+      // apply
+      const bool ragged = t < tri_end;
+      const uint32_t tcap = ragged ? t + 1 : ~0u;
+      if (ragged && lane >= t - gbase) z_text = ~0u;  // pattern not before the text
       // per-text copies the compiler cannot see through, so that the per-step
       // length and resume tests are formed inside the loop instead of being
       // hoisted into (spilled) registers
@@ -279,9 +291,19 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
       TCR_CORE(J)                                                              \
     }                                                                          \
     if (alive) {
+// A wave with no lane within k after step J < 8 jumps: every text sharing
+// this text's first J+1 residues ends the same way, so the walk continues at
+// the end of that prefix group (nxt[J]; the record's own prefix length with
+// it is the state the next text reuses).
 #define TCR_CLOSE(J)                                                           \
     } else {                                                                   \
       ex = (J);                                                                \
+      if constexpr ((J) < kSkipDepths) {                                       \
+        tn = min(max(tr.nxt[(J)], t + 1), tcap);                               \
+        lcp_next = (J) == 0 ? 0u : (tr.len >> (10 + 3 * ((J) - 1))) & 7u;      \
+      } else {                                                                 \
+        lcp_next = (tr.len >> 6) & 15u;                                        \
+      }                                                                        \
     }                                                                          \
   }
 
@@ -297,18 +319,8 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
       TCR_CLOSE(7) TCR_CLOSE(6) TCR_CLOSE(5) TCR_CLOSE(4) TCR_CLOSE(3) TCR_CLOSE(2) TCR_CLOSE(1)
       TCR_CLOSE(0)
 
-      // common prefix of this text with the next visited one (from the
-      // record's packed lengths): the steps the next text can reuse
-      uint32_t lcp_next = (tr.len >> 6) & 15u;
-      if (ex < 32) {
-        // every text sharing this text's first ex+1 residues ends at the same
-        // step with no lane within k: jump past that prefix group (possible
-        // while the set of valid lanes cannot grow)
-        if (ex < (uint32_t)kSkipDepths && can_skip) {
-          tn = max(load_const(tnxt, 16 * t + ex), t + 1);
-          lcp_next = ex == 0 ? 0u : (tr.len >> (10 + 3 * (ex - 1))) & 7u;
-        }
-      } else {
+      if (ex == 32) {
+        lcp_next = (tr.len >> 6) & 15u;
         // all n steps ran: the state after step n-1 (stack slot or rolling)
         uint32_t fZ = Z;
 #pragma unroll
@@ -331,7 +343,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
           staged += nh;
         }
       }
-      r = can_skip ? min(lcp_next, (uint32_t)kDepth) : 0u;
+      r = ragged ? 0u : min(lcp_next, (uint32_t)kDepth);
       t = tn;
 #undef TCR_OPEN
 #undef TCR_CLOSE
