@@ -12,8 +12,9 @@ sorted edge list + degrees).  Prints ONE JSON line.
                  two waves of a SIMD issue plain 32-bit ops per 4 clocks);
                  its algorithmic work = the text steps of the sorted-text walk
                  with prefix-group jumps x 64 lanes x 12 VALU instructions per
-                 bit-vector step (wave steps counted exactly by the CPU work
-                 model in bench_model.json)
+                 bit-vector step (13 where two 16-bit patterns share a lane;
+                 wave steps counted exactly by the CPU work model in
+                 bench_model.json)
   cpu_baseline   the CPU oracle (full DP, all host cores) on a bounded sample
                  of rows of the same workload
   serve / batch  the served and batched forms (see their sections)
@@ -40,6 +41,7 @@ METRIC = "pairs/s + edges/s at N=8e5,k=1 vs VALU roofline; p50/p99 query latency
 PEAK_LANE_OPS = 256 * 128 * 2.4e9         # 32-bit VALU lane-instructions per second (dual issue)
 WAVE = 64
 T_STEP_INSTR = 12                          # gfx950 VALU instructions per Myers/Hyyro step
+T_STEP_INSTR_PACKED = 13                   # the same with two 16-bit patterns per lane (one more)
 T_STEP_LOGICAL = 17                        # word operations of the published step
 
 
@@ -311,9 +313,13 @@ def main():
     assert all(i["evaluated_pairs"] == ev_pairs for i in infos)
     trav = model["traversal"]
     T_used = infos[-1]["texts_per_item"]
-    if T_used != trav["texts_per_item"]:
-        log(f"schedule uses {T_used} texts per item, the work model {trav['texts_per_item']}: roofline not priced")
-    work_instr = trav["wave_steps"] * WAVE * T_STEP_INSTR
+    pack_used = bool(infos[-1]["pack"])
+    priced = T_used == trav["texts_per_item"] and pack_used == trav["pack"]
+    if not priced:
+        log(f"schedule (T={T_used}, pack={pack_used}) differs from the work model's "
+            f"(T={trav['texts_per_item']}, pack={trav['pack']}): roofline not priced")
+    plain_steps = trav["wave_steps"] - trav["wave_steps_packed"]
+    work_instr = WAVE * (plain_steps * T_STEP_INSTR + trav["wave_steps_packed"] * T_STEP_INSTR_PACKED)
     achieved = work_instr / (pk_ms * 1e-3)
     pair_work = ev_pairs * model["mean_exit_steps"] * T_STEP_INSTR
     logical = n * (n - 1) // 2
@@ -338,22 +344,27 @@ def main():
         "evaluated_pairs": ev_pairs,
         "evaluated_pairs_per_s": ev_pairs / step_s,
         "pair_kernel_ms": pk_ms,
-        "schedule": {kk: infos[-1][kk] for kk in ("texts_per_item", "waves_per_simd", "peq_lds")},
+        "schedule": {kk: infos[-1][kk] for kk in ("texts_per_item", "waves_per_simd", "peq_lds", "pack")},
         "roofline": {
             "bound": "alu",
-            "achieved": achieved / 1e12 if T_used == trav["texts_per_item"] else None,
+            "achieved": achieved / 1e12 if priced else None,
             "peak": PEAK_LANE_OPS / 1e12,
             "unit": "T lane-instr/s",
-            "frac": achieved / PEAK_LANE_OPS if T_used == trav["texts_per_item"] else None,
+            "frac": achieved / PEAK_LANE_OPS if priced else None,
             "traffic": counted_traffic(T_used),
             "traffic_unit": "B per launch",
             "kernel": "k_pairs",
-            "work_per_unit": f"{WAVE} lanes x {T_STEP_INSTR} VALU instr per wave text step",
+            "work_per_unit": f"{WAVE} lanes x {T_STEP_INSTR} VALU instr per wave text step "
+                             f"({T_STEP_INSTR_PACKED} when two patterns share a lane)",
             "units_per_launch": trav["wave_steps"],
+            "units_packed": trav["wave_steps_packed"],
             "visited_wave_texts": trav["visited_texts"],
-            "frac_logical_17op": achieved / PEAK_LANE_OPS * T_STEP_LOGICAL / T_STEP_INSTR,
+            # the published step's 17 word operations per pattern and text step
+            # (a packed wave step covers 128 patterns)
+            "frac_logical_17op": (WAVE * T_STEP_LOGICAL * (plain_steps + 2 * trav["wave_steps_packed"])
+                                  / (pk_ms * 1e-3) / PEAK_LANE_OPS) if priced else None,
             "peak_measured": peak_meas / 1e12,
-            "frac_of_measured": achieved / peak_meas,
+            "frac_of_measured": achieved / peak_meas if priced else None,
             "per_pair_work_lane_instr": pair_work,
             "traversal_saving": pair_work / work_instr,
         },

@@ -95,6 +95,8 @@ typedef struct {
 
 #define TCRNET_F_NO_AUTOTUNE 1u   /* never consult or run the autotuner */
 #define TCRNET_F_PEQ_LDS 2u       /* keep pattern bit masks in LDS instead of VGPRs */
+#define TCRNET_F_NO_PACK 4u       /* one pattern per lane also for patterns of <= 16
+                                     residues (default: two, in 16-bit halves) */
 
 /* Create a context on HIP device `device` (stream, workspace, options).
    Fails with TCRNET_EDEVICE if the device is absent or not gfx950. */
@@ -164,6 +166,7 @@ typedef struct {
   uint32_t texts_per_item;
   uint32_t waves_per_simd;
   uint32_t peq_lds;
+  uint32_t pack;         /* 1: patterns of <= 16 residues ran two per lane */
 } tcrnet_build_info;
 TCRNET_API int32_t tcrnet_graph_info(const tcrnet_graph* g, tcrnet_build_info* info);
 /* Counters of the context's most recent build of any kind. */

@@ -186,12 +186,13 @@ class Oracle:
 
     def work_items(self, seqs, seq, gend, items, k: int, resume: int = 0):
         """Work model: (text steps, texts visited) of each work item
-        (rows of items: gbase, np, tb, te, tri over sorted positions; seq:
-        sorted position -> input id; gend: n x 8 prefix-group ends; resume:
-        steps a visited text can take over from the previous one)."""
+        (rows of items: gbase, np, tb, te, tri, width over sorted positions,
+        width = patterns per item; seq: sorted position -> input id; gend:
+        n x 8 prefix-group ends; resume: steps a visited text can take over
+        from the previous one)."""
         seq = np.ascontiguousarray(seq, dtype=np.uint32)
         gend = np.ascontiguousarray(gend, dtype=np.uint32)
-        items = np.ascontiguousarray(items, dtype=np.uint32).reshape(-1, 5)
+        items = np.ascontiguousarray(items, dtype=np.uint32).reshape(-1, 6)
         steps = np.zeros(max(1, len(items)), dtype=np.uint64)
         texts = np.zeros(max(1, len(items)), dtype=np.uint64)
         chars = np.ascontiguousarray(seqs.chars) if seqs.chars.size else np.zeros(1, np.uint8)

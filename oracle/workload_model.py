@@ -127,13 +127,23 @@ def group_ends(M, L, order):
     return gend
 
 
-def plan_items(L_sorted, k: int, T: int) -> np.ndarray:
+PACK_MAX_LEN = 16    # patterns this short run two to a lane (k < 16)
+
+
+def group_width(m: int, k: int, pack: bool) -> int:
+    """Patterns per work item of a bucket pair with pattern length m."""
+    return 2 * WAVE if pack and m <= PACK_MAX_LEN and k < 16 else WAVE
+
+
+def plan_items(L_sorted, k: int, T: int, pack: bool = True) -> np.ndarray:
     """The pair kernel's work items of a one-segment build: rows (gbase, np,
-    tb, te, tri) over sorted positions."""
+    tb, te, tri, width) over sorted positions; width = patterns per item
+    (64, or 128 when two patterns share a lane)."""
     cnt = np.bincount(L_sorted, minlength=34)
     off = np.concatenate([[0], np.cumsum(cnt)])
     rows = []
     for m in range(1, 33):
+        W = group_width(m, k, pack)
         for delta in range(0, k + 1):
             nl = m - delta
             if nl < 1:
@@ -142,14 +152,14 @@ def plan_items(L_sorted, k: int, T: int) -> np.ndarray:
             if delta > 0:
                 if npat == 0 or ntxt == 0:
                     continue
-                g = np.arange((npat + WAVE - 1) // WAVE)
+                g = np.arange((npat + W - 1) // W)
                 c = np.arange((ntxt + T - 1) // T)
                 G, C = np.meshgrid(g, c, indexing="ij")
-                gb = off[m] + WAVE * G
+                gb = off[m] + W * G
                 tb = off[nl] + T * C
                 te = np.minimum(off[nl] + ntxt, tb + T)
-                npg = np.minimum(WAVE, npat - WAVE * G)
-                rows.append(np.stack([gb, npg, tb, te, np.zeros_like(gb)], -1).reshape(-1, 5))
+                npg = np.minimum(W, npat - W * G)
+                rows.append(np.stack([gb, npg, tb, te, np.zeros_like(gb), np.full_like(gb, W)], -1).reshape(-1, 6))
             else:
                 if npat < 2:
                     continue
@@ -157,28 +167,29 @@ def plan_items(L_sorted, k: int, T: int) -> np.ndarray:
                     nrow = min(T, npat - bk * T)
                     p0 = off[m] + bk * T
                     ntb = npat - bk * T
-                    g = np.arange((nrow + WAVE - 1) // WAVE)
+                    g = np.arange((nrow + W - 1) // W)
                     c = np.arange((ntb + T - 1) // T)
                     G, C = np.meshgrid(g, c, indexing="ij")
-                    gb = p0 + WAVE * G
+                    gb = p0 + W * G
                     tb = p0 + T * C
                     te = np.minimum(p0 + ntb, tb + T)
                     tb = np.maximum(tb, gb + 1)
-                    npg = np.minimum(WAVE, nrow - WAVE * G)
-                    rows.append(np.stack([gb, npg, tb, te, np.ones_like(gb)], -1).reshape(-1, 5))
+                    npg = np.minimum(W, nrow - W * G)
+                    rows.append(np.stack([gb, npg, tb, te, np.ones_like(gb), np.full_like(gb, W)], -1).reshape(-1, 6))
     if not rows:
-        return np.zeros((0, 5), dtype=np.uint32)
+        return np.zeros((0, 6), dtype=np.uint32)
     return np.concatenate(rows).astype(np.uint32)
 
 
-def traversal(seqs, k: int, T: int, max_items: int, seed: int = 1, resume: int = RESUME) -> dict:
+def traversal(seqs, k: int, T: int, max_items: int, seed: int = 1, resume: int = RESUME,
+              pack: bool = True) -> dict:
     """Text steps and visited texts of the traversal over all work items
     (exact when the items number at most max_items, else estimated from a
     seeded uniform sample of max_items items)."""
     M, L = code_matrix(seqs)
     order = sorted_order(M, L)
     gend = group_ends(M, L, order)
-    items = plan_items(L[order], k, T)
+    items = plan_items(L[order], k, T, pack)
     total = len(items)
     exact = total <= max_items
     if exact:
@@ -189,8 +200,12 @@ def traversal(seqs, k: int, T: int, max_items: int, seed: int = 1, resume: int =
     steps = steps.astype(np.float64)
     texts = texts.astype(np.float64)
     scale = total / max(1, len(pick))
-    out = {"texts_per_item": T, "resume_depth": resume, "items": total, "items_modelled": int(len(pick)), "exact": bool(exact),
-           "wave_steps": float(steps.sum() * scale), "visited_texts": float(texts.sum() * scale)}
+    packed = pick[:, 5] > WAVE
+    out = {"texts_per_item": T, "resume_depth": resume, "pack": bool(pack), "items": total,
+           "items_packed": int((items[:, 5] > WAVE).sum()), "items_modelled": int(len(pick)),
+           "exact": bool(exact),
+           "wave_steps": float(steps.sum() * scale), "visited_texts": float(texts.sum() * scale),
+           "wave_steps_packed": float(steps[packed].sum() * scale)}
     out["stderr_wave_steps"] = 0.0 if exact else float(steps.std(ddof=1) * total / np.sqrt(len(pick)))
     return out
 

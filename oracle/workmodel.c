@@ -3,15 +3,17 @@
  * (used by oracle/workload_model.py to price a launch; no code is shared with
  * the HIP library).
  *
- * A work item is a group of up to 64 patterns and a run of texts of one
- * length bucket, the texts in sorted order (length, residues).  For each
+ * A work item is a group of up to `width` patterns (64, or 128 when two
+ * patterns share a lane) and a run of texts of one length bucket, the texts
+ * in sorted order (length, residues).  For each
  * visited text the wave needs as many text steps as its last lane needs
  * before the final-diagonal bound exceeds k (oracle_exit_step), or all n
  * steps when some lane ends within k.  When every lane ended early after e
  * residues, all texts sharing those first e residues end the same way, so
  * the walk continues at the end of that prefix group (group ends for
- * e = 1..8, given by the caller); in a triangle item this holds only once all
- * 64 lanes are valid (pattern before text).  A visited text whose first r
+ * e = 1..8, given by the caller); in a triangle item this holds only once the
+ * text lies `width` positions past the group start (every pattern of the
+ * group before it).  A visited text whose first r
  * residues equal those of the previous visited text of the item starts at
  * step r (r capped at `resume`; 0 for the item's first text and after a text
  * whose set of valid lanes differs from the next one's).
@@ -36,8 +38,8 @@ static int common_prefix(const uint8_t* a, const uint8_t* b, int n, int cap) {
  * group.  Returns the text steps; *texts = texts visited. */
 
 static uint64_t wm_item(const uint8_t* chars, const uint64_t* offsets, const uint32_t* seq, const uint32_t* gend,
-                        uint32_t gbase, uint32_t np, uint32_t tb, uint32_t te, int tri, int k, int resume,
-                        uint64_t* texts) {
+                        uint32_t gbase, uint32_t np, uint32_t tb, uint32_t te, int tri, uint32_t width, int k,
+                        int resume, uint64_t* texts) {
   uint64_t steps = 0, visited = 0;
   uint32_t t = tb;
   int prev_ok = 0;       /* previous visited text may pass its state on */
@@ -63,7 +65,7 @@ static uint64_t wm_item(const uint8_t* chars, const uint64_t* offsets, const uin
     }
     steps += (full ? (uint64_t)n : (uint64_t)e) - (uint64_t)r;
     visited += 1;
-    const int can_skip = !tri || t - gbase >= 64;
+    const int can_skip = !tri || t - gbase >= width;
     prev_ok = can_skip;
     prev = t;
     uint32_t tn = t + 1;
@@ -77,12 +79,13 @@ static uint64_t wm_item(const uint8_t* chars, const uint64_t* offsets, const uin
   return steps;
 }
 
-/* count items, item q = (gbase, np, tb, te, tri) at items[5q..5q+4]. */
+/* count items, item q = (gbase, np, tb, te, tri, width) at items[6q..6q+5]. */
 void wm_items(const uint8_t* chars, const uint64_t* offsets, const uint32_t* seq, const uint32_t* gend,
               const uint32_t* items, int64_t count, int k, int resume, uint64_t* steps, uint64_t* texts) {
 #pragma omp parallel for schedule(dynamic, 1)
   for (int64_t q = 0; q < count; ++q) {
-    const uint32_t* it = items + 5 * q;
-    steps[q] = wm_item(chars, offsets, seq, gend, it[0], it[1], it[2], it[3], (int)it[4], k, resume, &texts[q]);
+    const uint32_t* it = items + 6 * q;
+    steps[q] = wm_item(chars, offsets, seq, gend, it[0], it[1], it[2], it[3], (int)it[4], it[5], k, resume,
+                       &texts[q]);
   }
 }

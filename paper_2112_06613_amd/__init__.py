@@ -19,6 +19,7 @@ LIB_PATH = os.path.join(_HERE, "libtcrnet.so")
 TCRNET_OK, TCRNET_EINVAL, TCRNET_ENOMEM, TCRNET_EDEVICE, TCRNET_ESTATE, TCRNET_ETRUNC = range(6)
 TCRNET_F_NO_AUTOTUNE = 1
 TCRNET_F_PEQ_LDS = 2
+TCRNET_F_NO_PACK = 4
 MAX_LEN = 32
 MAX_K = 31
 
@@ -50,7 +51,8 @@ class tcrnet_build_info(ctypes.Structure):
     _fields_ = [("evaluated_pairs", ctypes.c_uint64), ("pair_kernel_ms", ctypes.c_double),
                 ("build_ms", ctypes.c_double), ("pair_launches", ctypes.c_uint32),
                 ("texts_per_item", ctypes.c_uint32), ("waves_per_simd", ctypes.c_uint32),
-                ("peq_lds", ctypes.c_uint32)]
+                ("peq_lds", ctypes.c_uint32),
+                ("pack", ctypes.c_uint32)]
 
 
 class tcrnet_result_info(ctypes.Structure):

@@ -63,6 +63,7 @@ Sched pick_sched(const tcrnet_ctx* ctx, uint64_t n, int k) {
   if (ctx->opts.texts_per_item) s.texts_per_item = ctx->opts.texts_per_item;
   if (ctx->opts.waves_per_simd) s.waves_per_simd = ctx->opts.waves_per_simd;
   if (ctx->opts.flags & TCRNET_F_PEQ_LDS) s.peq_lds = true;
+  if (ctx->opts.flags & TCRNET_F_NO_PACK) s.pack = false;
   // whole waves of 64 texts per item keep triangle items non-empty
   s.texts_per_item = std::max<uint32_t>(64, (s.texts_per_item + 63) / 64 * 64);
   s.waves_per_simd = std::min<uint32_t>(8, std::max<uint32_t>(1, s.waves_per_simd));
@@ -80,6 +81,7 @@ int32_t run_pipeline(tcrnet_ctx* ctx, Pipeline& pl, PipeParams pp, hipStream_t s
   inf.texts_per_item = sched.texts_per_item;
   inf.waves_per_simd = sched.waves_per_simd;
   inf.peq_lds = sched.peq_lds ? 1 : 0;
+  inf.pack = sched.pack ? 1 : 0;
   if (pp.n == 0) {
     *E = 0;
     if (info) *info = inf;
@@ -378,6 +380,7 @@ int32_t tcrnet_build_batch(tcrnet_ctx* ctx, const tcrnet_seqs* reps, uint32_t n_
   info.texts_per_item = sched.texts_per_item;
   info.waves_per_simd = sched.waves_per_simd;
   info.peq_lds = sched.peq_lds;
+  info.pack = sched.pack;
   uint64_t E = 0;
   if (n > 0) {
     for (int attempt = 0; attempt < 2; ++attempt) {
@@ -387,7 +390,8 @@ int32_t tcrnet_build_batch(tcrnet_ctx* ctx, const tcrnet_seqs* reps, uint32_t n_
       pp.d_pairs = ctx->out_pairs.as<uint32_t>();
       // one HIP graph for the whole launch sequence, re-captured only when
       // the shape or a buffer changes
-      BatchKey key{n, pp.n_seg, k, sched.texts_per_item, sched.waves_per_simd, sched.peq_lds, pp.capacity,
+      BatchKey key{n, pp.n_seg, k, sched.texts_per_item, sched.waves_per_simd, sched.peq_lds, sched.pack,
+                   pp.capacity,
                    ctx->pipe.rec.p, ctx->pipe.edges.p, ctx->pipe.tmp.p, ctx->out_pairs.p, ctx->in_data.p};
       if (!ctx->batch_exec || !(key == ctx->batch_key)) {
         if (ctx->batch_exec) {

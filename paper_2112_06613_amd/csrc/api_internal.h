@@ -16,11 +16,11 @@ struct BatchKey {
   uint32_t n = 0, n_seg = 0;
   int k = 0;
   uint32_t T = 0, W = 0;
-  bool lds = false;
+  bool lds = false, pack = false;
   uint64_t capacity = 0;
   void *rec = nullptr, *edges = nullptr, *tmp = nullptr, *pairs = nullptr, *data = nullptr;
   bool operator==(const BatchKey& o) const {
-    return n == o.n && n_seg == o.n_seg && k == o.k && T == o.T && W == o.W && lds == o.lds &&
+    return n == o.n && n_seg == o.n_seg && k == o.k && T == o.T && W == o.W && lds == o.lds && pack == o.pack &&
            capacity == o.capacity && rec == o.rec && edges == o.edges && tmp == o.tmp && pairs == o.pairs &&
            data == o.data;
   }

@@ -12,6 +12,7 @@ constexpr int kBlock = 256;      // threads per block of the pair kernel (4 wave
 constexpr uint32_t kQueryTag = 0x80000000u;  // id bit marking the query side
 
 constexpr int kSkipDepths = 8;   // prefix depths with a group-end pointer
+constexpr uint32_t kPackMaxLen = 16;  // patterns this short go two to a lane
 constexpr uint32_t kLenMask = 63u;  // length bits of SeqRec::len
 
 // One sequence as the pair kernel reads it (64 bytes, read with one scalar
@@ -57,6 +58,8 @@ struct alignas(16) Desc {
   uint32_t m, n;         // lengths
   uint32_t tri;          // 1: pairs (p, t) with p < t only
   uint32_t chunks;       // ceil(nt / texts_per_item)
+  uint32_t pack;         // patterns per lane: 2 (m <= kPackMaxLen) or 1;
+                         // a group is 64 * pack patterns
   uint64_t item_base;    // first item of this descriptor
   uint64_t items;        // groups * chunks
 };

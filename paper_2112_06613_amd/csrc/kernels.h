@@ -61,9 +61,11 @@ void launch_gather(const SeqRec* rec, const uint32_t* val, const uint64_t* skey,
 // plan header; more than max_desc descriptors sets plan->pad = 1.
 uint32_t plan_max_desc_self(uint32_t n_seg, int k, uint32_t texts_per_item, uint64_t n);
 uint32_t plan_max_desc_cross(int k);
+// pack: bucket pairs whose patterns have at most kPackMaxLen residues run two
+// patterns per lane (groups of 128).
 void launch_plan(const PlanPart* d_parts, uint32_t n_parts, const PlanPart& inline_part, int k,
-                 uint32_t texts_per_item, Desc* descs, uint64_t* item_base, uint32_t max_desc, Plan* plan,
-                 hipStream_t st);
+                 uint32_t texts_per_item, bool pack, Desc* descs, uint64_t* item_base, uint32_t max_desc,
+                 Plan* plan, hipStream_t st);
 
 // Steps a4-a6: the pair kernel (persistent grid).
 struct PairArgs {

@@ -27,13 +27,17 @@
 // Layout of the work: a wave holds 64 consecutive patterns of one length
 // bucket (one per lane, their Peq tables in VGPRs, or in LDS) and walks the
 // texts of a chunk of another (or the same) bucket; each text is
-// wave-uniform and is read with scalar loads into SGPRs.  Sequences are
-// sorted by (length, residues), so the 64 patterns of a wave share prefixes
-// and leave a text at nearly the same step.  Pattern = the longer string of
-// the pair when lengths differ (it exits earliest).
+// wave-uniform and is read with scalar loads into SGPRs.  Patterns of at
+// most 16 residues go two to a lane (128 per wave, one in each 16-bit half
+// of every word): the per-text bookkeeping, which is scalar and bounds the
+// kernel, is then shared by twice the patterns.  Sequences are sorted by
+// (length, residues), so the patterns of a wave share prefixes and leave a
+// text at nearly the same step.  Pattern = the longer string of the pair
+// when lengths differ (it exits earliest).
 //
-// Output: lanes whose final distance is <= k are compacted with one ballot,
-// one atomic add per wave, and consecutive edge slots (coalesced writes).
+// Output: patterns whose final distance is <= k are compacted with a ballot
+// per half, staged in LDS per wave, and take consecutive global edge slots
+// with one atomic add per staged batch (coalesced writes).
 #include "kernels.h"
 
 namespace tcr {
@@ -94,10 +98,24 @@ __device__ __forceinline__ uint32_t twice_plus1(uint32_t x) {
   return r;
 }
 
-// popcount(z) <= k, with the cheap forms for k = 1 (at most one bit set) and
-// k = 2 (at most two) selected at compile time.
+// Two patterns per lane (patterns of at most 16 residues): pattern A in
+// bits 0-15 and pattern B in bits 16-31 of every bit-vector word.  The
+// bitwise operations of a step act on both halves alike; the one addition
+// and the two shifts by one must not carry from bit 15 into bit 16, so they
+// are 16-bit packed adds (v_pk_add_u16, one instruction for both halves).
+typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+__device__ __forceinline__ uint32_t pk_add(uint32_t a, uint32_t b) {
+  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, a) + __builtin_bit_cast(u16x2, b));
+}
+__device__ __forceinline__ uint32_t pk_dec(uint32_t a) {
+  const u16x2 one = {1, 1};
+  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, a) - one);
+}
+
+// popcount(z) <= k for one miss word, with the cheap forms for k = 1 (at
+// most one bit set) and k = 2 (at most two) selected at compile time.
 template <int kMode>
-__device__ __forceinline__ bool within_k_impl(uint32_t z, int k) {
+__device__ __forceinline__ bool within_k_word(uint32_t z, int k) {
   if (kMode == 1) return (z & (z - 1u)) == 0u;
   if (kMode == 2) {
     const uint32_t y = z & (z - 1u);
@@ -105,7 +123,27 @@ __device__ __forceinline__ bool within_k_impl(uint32_t z, int k) {
   }
   return __popc(z) <= k;
 }
-#define within_k(z, kk) within_k_impl<kMode>((z), (kk))
+
+// The lane has a pattern still within k: the word, or either 16-bit half of
+// a two-pattern word (a half is zero after clearing its lowest k set bits).
+template <int kMode, int kPack>
+__device__ __forceinline__ bool within_k_lane(uint32_t z, int k) {
+  if constexpr (kPack == 1) {
+    return within_k_word<kMode>(z, k);
+  } else {
+    if (kMode == 1 || kMode == 2) {
+      uint32_t y = z & pk_dec(z);
+      if (kMode == 2) y &= pk_dec(y);
+      return min(y & 0xFFFFu, y >> 16) == 0u;
+    }
+    return (int)min(__popc(z & 0xFFFFu), __popc(z >> 16)) <= k;
+  }
+}
+
+template <int V>
+struct PackTag {
+  static constexpr int value = V;
+};
 
 // kMode: the within-k test on the miss word: 1 (k = 1), 2 (k = 2), 0 (any k:
 // popcount).
@@ -147,45 +185,32 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     staged = 0;
   };
 
-  // a wave starts on its own queue stripe and moves on when it runs dry; it
-  // stops after finding every stripe empty in a row
-  uint32_t stripe = (blockIdx.x * (kBlock / kWave) + rfl(wid)) % kQueueStripes;
-  uint32_t empty = 0;
-  for (;;) {
-    uint64_t j = 0;
-    if (lane == 0) j = atomicAdd(&cnt->queue[stripe].next, 1ull);
-    j = rfl64(j);
-    const uint64_t item = j * kQueueStripes + stripe;
-    if (item >= total) {
-      if (++empty == (uint32_t)kQueueStripes) break;
-      stripe = (stripe + 1) % kQueueStripes;
-      continue;
-    }
-    empty = 0;
-
-    // descriptor holding this item: largest di with item_base[di] <= item
-    uint32_t lo = 0, hi = nd;
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (item_base[mid] <= item) lo = mid; else hi = mid;
-    }
-    const Desc d = descs[lo];
+  // One work item: pattern group g (kPack * 64 patterns, kPack per lane)
+  // against text chunk c of descriptor d.
+  auto run_item = [&](auto pack_tag, const Desc& d, uint32_t g, uint32_t c) {
+    constexpr int kPack = decltype(pack_tag)::value;
+    constexpr uint32_t kGroup = kWave * kPack;  // patterns of a work item
     const SeqRec* prec = d.prec;
     const PeqRec* ppeq = d.ppeq;
     const SeqRec* trec = d.trec;
-    const uint32_t local = (uint32_t)(item - d.item_base);
-    const uint32_t g = local / d.chunks;
-    const uint32_t c = local - g * d.chunks;
-    const uint32_t gbase = d.p0 + g * kWave;
-    const bool lane_ok = g * kWave + lane < d.np;
-    const uint32_t p = lane_ok ? gbase + lane : d.p0;
-    const uint64_t lane_mask = __ballot(lane_ok);
+    const uint32_t gbase = d.p0 + g * kGroup;
+    // lane's patterns: gbase + lane (bits 0-15 when packed), gbase + 64 + lane
+    // (bits 16-31); a lane outside the item reads pattern d.p0 and is masked
+    const bool ok0 = g * kGroup + lane < d.np;
+    const bool ok1 = kPack == 2 && g * kGroup + kWave + lane < d.np;
+    const uint32_t p0 = ok0 ? gbase + lane : d.p0;
+    const uint32_t p1 = ok1 ? gbase + kWave + lane : d.p0;
 
     uint32_t eq[kAlpha];
     {
-      const PeqRec pr = load_global(ppeq, p);
+      const PeqRec pr = load_global(ppeq, p0);
 #pragma unroll
       for (int a = 0; a < kAlpha; ++a) eq[a] = pr.eq[a];
+      if constexpr (kPack == 2) {
+        const PeqRec ph = load_global(ppeq, p1);
+#pragma unroll
+        for (int a = 0; a < kAlpha; ++a) eq[a] |= ph.eq[a] << 16;
+      }
     }
     if (kPeqLds) {
 #pragma unroll
@@ -194,20 +219,28 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     }
 
     const uint32_t m = d.m, n = d.n;  // m >= n: the pattern is the longer string
-    const uint32_t Mm = low_mask(m);
     const uint32_t delta = m - n;     // final diagonal: row = column + delta
+    const uint32_t Mm = kPack == 2 ? low_mask(m) * 0x10001u : low_mask(m);
     // Miss word: bit delta+J set when text step J missed on the final
     // diagonal, bits below delta set from the start, so popcount(Z) is the
-    // diagonal cell D[delta+j][j] after j steps and D[m][n] = lev at the end.
-    // A lane outside the item starts at ~0 (never within k).
-    const uint32_t z_item = lane_ok ? (1u << delta) - 1u : ~0u;
+    // diagonal cell D[delta+j][j] after j steps and D[m][n] = lev at the end
+    // (per 16-bit half when packed).  A pattern outside the item starts with
+    // all its bits set (never within k).
+    uint32_t z_item, m_item;
+    if constexpr (kPack == 2) {
+      z_item = (ok0 ? (1u << delta) - 1u : 0xFFFFu) | ((ok1 ? (1u << delta) - 1u : 0xFFFFu) << 16);
+      m_item = (1u << delta) * 0x10001u;
+    } else {
+      z_item = ok0 ? (1u << delta) - 1u : ~0u;
+      m_item = 1u << delta;
+    }
     const uint32_t tb0 = d.t0 + c * T;
     const uint32_t te = min(d.t0 + d.nt, tb0 + T);
     uint32_t tb = tb0;
     if (d.tri && tb < gbase + 1) tb = gbase + 1;
     // in a triangle item, texts before tri_end still have patterns at or
-    // after them in the wave (those lanes are masked off)
-    const uint32_t tri_end = d.tri ? gbase + kWave : 0u;
+    // after them in the item (those patterns are masked off)
+    const uint32_t tri_end = d.tri ? gbase + kGroup : 0u;
     const SeqRec* tbase = trec + tb0;  // this item's text records
 
     // Register stack of the state after each of the first kDepth text steps.
@@ -229,38 +262,56 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
       // record's packed lengths): the steps the next text can reuse
       uint32_t lcp_next = 0;
       uint32_t z_text = z_item;
-      // ragged: the set of valid lanes still grows with the next texts, so
-      // neither jumps (tcap keeps them at the next text) nor resumed state
-      // apply
+      // ragged: the set of valid patterns still grows with the next texts,
+      // so neither jumps (tcap keeps them at the next text) nor resumed
+      // state apply
       const bool ragged = t < tri_end;
       const uint32_t tcap = ragged ? t + 1 : ~0u;
-      if (ragged && lane >= t - gbase) z_text = ~0u;  // pattern not before the text
+      if (ragged) {  // patterns not before the text are masked
+        const uint32_t dt = t - gbase;
+        if constexpr (kPack == 2) {
+          if (lane >= dt) z_text |= 0xFFFFu;
+          if (lane + kWave >= dt) z_text |= 0xFFFF0000u;
+        } else {
+          if (lane >= dt) z_text = ~0u;
+        }
+      }
       // per-text copies the compiler cannot see through, so that the per-step
       // length and resume tests are formed inside the loop instead of being
       // hoisted into (spilled) registers
       uint32_t nn = n, rr = r;
       asm volatile("" : "+s"(nn), "+s"(rr));
-      uint32_t mJ = (1u << delta) << rr;  // diagonal row bit of the first computed step
-      uint32_t ex = 32;                    // text step after which no lane was within k (32: none)
+      uint32_t mJ = m_item << rr;  // diagonal row bit(s) of the first computed step
+      uint32_t ex = 32;            // text step after which no lane was within k (32: none)
       bool alive = true;
       uint32_t VP = Mm, VN = 0, Z = z_text;
 
 // One Myers/Hyyro text step on character J, then the miss accounting: OR the
-// diagonal row's miss bit into Z; alive: some lane with popcount(Z) <= k.
+// diagonal row's miss bit into Z; alive: some lane still within k.
 #define TCR_EQ(cc) (kPeqLds ? wave_eq[(cc) * kWave + lane] : eq[(cc)])
 #define TCR_CODE(q) ((tr.w[(q) / 6] >> (5 * ((q) % 6))) & 31u)
 #define TCR_CORE(J)                                                            \
   {                                                                            \
     const uint32_t Eq = TCR_EQ(TCR_CODE(J));                                   \
-    const uint32_t D0 = (((Eq & VP) + VP) ^ VP) | Eq | VN;                     \
-    const uint32_t HP = VN | ~(D0 | VP);                                       \
-    const uint32_t HN = D0 & VP;                                               \
-    const uint32_t X = twice_plus1(HP);                                        \
-    VN = X & D0;                                                               \
-    VP = twice(HN) | ~(X | D0);                                                \
+    uint32_t D0;                                                               \
+    if constexpr (kPack == 2) {                                                \
+      D0 = (pk_add(Eq & VP, VP) ^ VP) | Eq | VN;                               \
+      const uint32_t HP = VN | ~(D0 | VP);                                     \
+      const uint32_t HN = D0 & VP;                                             \
+      const uint32_t X = pk_add(HP, HP) | 0x00010001u;                         \
+      VN = X & D0;                                                             \
+      VP = pk_add(HN, HN) | ~(X | D0);                                         \
+    } else {                                                                   \
+      D0 = (((Eq & VP) + VP) ^ VP) | Eq | VN;                                  \
+      const uint32_t HP = VN | ~(D0 | VP);                                     \
+      const uint32_t HN = D0 & VP;                                             \
+      const uint32_t X = twice_plus1(HP);                                      \
+      VN = X & D0;                                                             \
+      VP = twice(HN) | ~(X | D0);                                              \
+    }                                                                          \
     Z |= ~D0 & mJ;                                                             \
     mJ = twice(mJ);                                                            \
-    alive = __ballot(within_k(Z, k)) != 0ull;                                  \
+    alive = __ballot((within_k_lane<kMode, kPack>(Z, k))) != 0ull;             \
   }
 #define TCR_SLOT(J) ((J) < kDepth ? (J) : 0)
 // Text steps are nested ifs (structured control flow, so every exit stays a
@@ -326,19 +377,32 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
 #pragma unroll
         for (int q = 0; q < kDepth; ++q)
           if (n == (uint32_t)q + 1) fZ = sZ[q];
-        // lanes whose final distance D[m][n] = popcount(Z) is within k
-        const bool hit = within_k(fZ, k);
-        const uint64_t hm = __ballot(hit);
-        if (hm) {
-          const uint32_t nh = (uint32_t)__popcll(hm);
+        // patterns whose final distance D[m][n] = popcount is within k
+        const uint32_t fz0 = kPack == 2 ? fZ & 0xFFFFu : fZ;
+        const bool hit0 = within_k_word<kMode>(fz0, k);
+        const bool hit1 = kPack == 2 && within_k_word<kMode>(fZ >> 16, k);
+        const uint64_t hm0 = __ballot(hit0);
+        const uint64_t hm1 = kPack == 2 ? __ballot(hit1) : 0ull;
+        if (hm0 | hm1) {
+          const uint32_t nh0 = (uint32_t)__popcll(hm0);
+          const uint32_t nh = nh0 + (uint32_t)__popcll(hm1);
           if (staged + nh > (uint32_t)kEdgeBuf) flush();
-          if (hit) {
-            const uint32_t pos = staged + (uint32_t)__popcll(hm & lt_mask);
+          const uint32_t* pid = reinterpret_cast<const uint32_t*>(prec);  // ids: word 7 of a record
+          if (hit0) {
+            const uint32_t pos = staged + (uint32_t)__popcll(hm0 & lt_mask);
             uint2 e;
-            e.x = load_global(reinterpret_cast<const uint32_t*>(prec), 16 * p + 7);  // pattern id, read on a hit only
+            e.x = load_global(pid, 16 * p0 + 7);  // pattern id, read on a hit only
             e.y = tr.id;
             wave_edge[pos] = e;
-            wave_dist[pos] = (uint8_t)__popc(fZ);
+            wave_dist[pos] = (uint8_t)__popc(fz0);
+          }
+          if (hit1) {
+            const uint32_t pos = staged + nh0 + (uint32_t)__popcll(hm1 & lt_mask);
+            uint2 e;
+            e.x = load_global(pid, 16 * p1 + 7);
+            e.y = tr.id;
+            wave_edge[pos] = e;
+            wave_dist[pos] = (uint8_t)__popc(fZ >> 16);
           }
           staged += nh;
         }
@@ -353,6 +417,36 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
 #undef TCR_CODE
     }
     if (kPeqLds) __builtin_amdgcn_wave_barrier();
+  };
+
+  // a wave starts on its own queue stripe and moves on when it runs dry; it
+  // stops after finding every stripe empty in a row
+  uint32_t stripe = (blockIdx.x * (kBlock / kWave) + rfl(wid)) % kQueueStripes;
+  uint32_t empty = 0;
+  for (;;) {
+    uint64_t j = 0;
+    if (lane == 0) j = atomicAdd(&cnt->queue[stripe].next, 1ull);
+    j = rfl64(j);
+    const uint64_t item = j * kQueueStripes + stripe;
+    if (item >= total) {
+      if (++empty == (uint32_t)kQueueStripes) break;
+      stripe = (stripe + 1) % kQueueStripes;
+      continue;
+    }
+    empty = 0;
+
+    // descriptor holding this item: largest di with item_base[di] <= item
+    uint32_t lo = 0, hi = nd;
+    while (hi - lo > 1) {
+      const uint32_t mid = (lo + hi) >> 1;
+      if (item_base[mid] <= item) lo = mid; else hi = mid;
+    }
+    const Desc d = descs[lo];
+    const uint32_t local = (uint32_t)(item - d.item_base);
+    const uint32_t g = local / d.chunks;
+    const uint32_t c = local - g * d.chunks;
+    if (d.pack == 2) run_item(PackTag<2>{}, d, g, c);
+    else run_item(PackTag<1>{}, d, g, c);
   }
   if (staged) flush();
 }

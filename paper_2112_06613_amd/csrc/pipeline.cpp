@@ -123,7 +123,8 @@ void stage_pairs(Pipeline& pl, const PlanPart* d_parts, uint32_t n_parts, const 
                  hipEvent_t ev1, bool keep_dist) {
   Counters* cnt = pl.cnt();
   launch_reset_work(cnt, st);
-  launch_plan(d_parts, n_parts, inline_part, k, sched.texts_per_item, pl.descs.as<Desc>(), pl.ibase.as<uint64_t>(),
+  launch_plan(d_parts, n_parts, inline_part, k, sched.texts_per_item, sched.pack, pl.descs.as<Desc>(),
+              pl.ibase.as<uint64_t>(),
               pl.desc_cap, pl.plan(), st);
   PairArgs a;
   a.descs = pl.descs.as<Desc>();

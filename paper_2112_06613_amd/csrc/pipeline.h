@@ -39,6 +39,7 @@ struct Sched {
   uint32_t texts_per_item = 16384;
   uint32_t waves_per_simd = 8;
   bool peq_lds = false;
+  bool pack = true;  // two patterns per lane for patterns of <= 16 residues
 };
 
 // Device buffers of one build pipeline (encode -> sort -> bucket -> plan ->

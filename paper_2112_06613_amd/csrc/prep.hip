@@ -205,13 +205,20 @@ struct Entry {
   const SeqRec* prec;
   const PeqRec* ppeq;
   const SeqRec* trec;
-  uint32_t p0, np, t0, nt, m, n, tri, ndesc;
+  uint32_t p0, np, t0, nt, m, n, tri, ndesc, pack;
   uint64_t items, pairs;
 };
 
-__device__ Entry entry_shape(const PlanPart& part, uint32_t e, int k, uint32_t T) {
+// Patterns per lane of a bucket pair whose patterns have length m.  A masked
+// half holds 16 set miss bits, which must exceed k.
+__device__ __forceinline__ uint32_t pack_for(uint32_t m, int k, uint32_t pack_ok) {
+  return pack_ok && m <= kPackMaxLen && k < 16 ? 2u : 1u;
+}
+
+__device__ Entry entry_shape(const PlanPart& part, uint32_t e, int k, uint32_t T, uint32_t pack_ok) {
   Entry r;
   r.ndesc = 0;
+  r.pack = 1;
   r.items = 0;
   r.pairs = 0;
   r.tri = 0;
@@ -237,10 +244,12 @@ __device__ Entry entry_shape(const PlanPart& part, uint32_t e, int k, uint32_t T
     r.np = off[cm + 1] - off[cm];
     r.t0 = off[cn];
     r.nt = off[cn + 1] - off[cn];
+    r.pack = pack_for(m, k, pack_ok);
+    const uint32_t G = 64u * r.pack;  // patterns per group
     if (delta > 0) {
       if (r.np == 0 || r.nt == 0) return r;
       r.ndesc = 1;
-      r.items = (uint64_t)((r.np + 63) / 64) * ((r.nt + T - 1) / T);
+      r.items = (uint64_t)((r.np + G - 1) / G) * ((r.nt + T - 1) / T);
       r.pairs = (uint64_t)r.np * r.nt;
     } else {
       if (r.np < 2) return r;
@@ -249,7 +258,7 @@ __device__ Entry entry_shape(const PlanPart& part, uint32_t e, int k, uint32_t T
       for (uint32_t bk = 0; bk < r.ndesc; ++bk) {
         const uint32_t rows = min(T, r.np - bk * T);
         const uint32_t cols = r.np - bk * T;
-        r.items += (uint64_t)((rows + 63) / 64) * ((cols + T - 1) / T);
+        r.items += (uint64_t)((rows + G - 1) / G) * ((cols + T - 1) / T);
       }
       r.pairs = (uint64_t)r.np * (r.np - 1) / 2;
     }
@@ -273,7 +282,8 @@ __device__ Entry entry_shape(const PlanPart& part, uint32_t e, int k, uint32_t T
       r.prec = part.b.srec; r.ppeq = part.b.speq; r.trec = part.a.srec;
     }
     r.ndesc = 1;
-    r.items = (uint64_t)((r.np + 63) / 64) * ((r.nt + T - 1) / T);
+    r.pack = pack_for(r.m, k, pack_ok);
+    r.items = (uint64_t)((r.np + 64u * r.pack - 1) / (64u * r.pack)) * ((r.nt + T - 1) / T);
     r.pairs = (uint64_t)na * nb;
   }
   return r;
@@ -297,8 +307,9 @@ __device__ uint64_t block_excl_scan_u64(uint64_t v, uint64_t* sh, uint64_t& tota
 
 __global__ __launch_bounds__(kPlanThreads) void k_plan(const PlanPart* __restrict__ parts, uint32_t n_parts,
                                                        PlanPart inline_part, int k, uint32_t T,
-                                                       Desc* __restrict__ descs, uint64_t* __restrict__ item_base,
-                                                       uint32_t max_desc, Plan* plan) {
+                                                       uint32_t pack_ok, Desc* __restrict__ descs,
+                                                       uint64_t* __restrict__ item_base, uint32_t max_desc,
+                                                       Plan* plan) {
   __shared__ uint64_t sh[kPlanThreads];
   if (!parts) {
     parts = nullptr;
@@ -314,7 +325,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(const PlanPart* __restric
       en.ndesc = 0;
       en.items = 0;
       en.pairs = 0;
-      if (e < n_entries) en = entry_shape(part, e, k, T);
+      if (e < n_entries) en = entry_shape(part, e, k, T, pack_ok);
       uint64_t tot_d, tot_i, tot_p;
       const uint64_t dpos = run_desc + block_excl_scan_u64(en.ndesc, sh, tot_d);
       const uint64_t ipos = run_items + block_excl_scan_u64(en.items, sh, tot_i);
@@ -327,6 +338,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(const PlanPart* __restric
         d.m = en.m;
         d.n = en.n;
         d.tri = en.tri;
+        d.pack = en.pack;
         if (!en.tri) {
           d.p0 = en.p0; d.np = en.np; d.t0 = en.t0; d.nt = en.nt;
           d.chunks = (en.nt + T - 1) / T;
@@ -342,7 +354,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(const PlanPart* __restric
             d.t0 = en.p0 + bk * T; d.nt = en.np - bk * T;
             d.chunks = (d.nt + T - 1) / T;
             d.item_base = ib;
-            d.items = (uint64_t)((rows + 63) / 64) * d.chunks;
+            d.items = (uint64_t)((rows + 64u * en.pack - 1) / (64u * en.pack)) * d.chunks;
             descs[dpos + bk] = d;
             item_base[dpos + bk] = ib;
             ib += d.items;
@@ -428,9 +440,9 @@ uint32_t plan_max_desc_self(uint32_t n_seg, int k, uint32_t T, uint64_t n) {
 uint32_t plan_max_desc_cross(int k) { return 32u * (uint32_t)(2 * k + 1); }
 
 void launch_plan(const PlanPart* d_parts, uint32_t n_parts, const PlanPart& inline_part, int k, uint32_t T,
-                 Desc* descs, uint64_t* item_base, uint32_t max_desc, Plan* plan, hipStream_t st) {
-  hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, st, d_parts, n_parts, inline_part, k, T, descs,
-                     item_base, max_desc, plan);
+                 bool pack, Desc* descs, uint64_t* item_base, uint32_t max_desc, Plan* plan, hipStream_t st) {
+  hipLaunchKernelGGL(k_plan, dim3(1), dim3(kPlanThreads), 0, st, d_parts, n_parts, inline_part, k, T,
+                     pack ? 1u : 0u, descs, item_base, max_desc, plan);
 }
 
 }  // namespace tcr

@@ -10,12 +10,12 @@ import oracle.workload_model as wm
 import synth
 
 
-def _setup(n, T, k, seed):
+def _setup(n, T, k, seed, pack=True):
     s = synth.repertoire(n, max(1, n // 10), seed)
     M, L = wm.code_matrix(s)
     order = wm.sorted_order(M, L)
     gend = wm.group_ends(M, L, order)
-    items = wm.plan_items(L[order], k, T)
+    items = wm.plan_items(L[order], k, T, pack)
     return s, L, order, gend, items
 
 
@@ -33,13 +33,14 @@ def test_sorted_order_and_group_ends():
             assert e == len(srt) or (len(srt[e]), srt[e][:d]) != key
 
 
-@pytest.mark.parametrize("k", [1, 2])
-def test_walk_is_exact_and_matches_python(orc, k):
-    s, L, order, gend, items = _setup(500, 128, k, 9 + k)
+@pytest.mark.parametrize("k,pack", [(1, True), (2, True), (1, False)])
+def test_walk_is_exact_and_matches_python(orc, k, pack):
+    s, L, order, gend, items = _setup(500, 128, k, 9 + k, pack)
+    assert (items[:, 5] > wm.WAVE).any() == pack
     strs = s.to_list()
     steps_c, texts_c = orc.work_items(s, order, gend, items, k, wm.RESUME)
     skipped = 0
-    for q, (gbase, npat, tb, te, tri) in enumerate(items.tolist()):
+    for q, (gbase, npat, tb, te, tri, width) in enumerate(items.tolist()):
         steps = visited = 0
         t = tb
         prev = None
@@ -56,9 +57,9 @@ def test_walk_is_exact_and_matches_python(orc, k):
                     r += 1
             steps += (len(b) if full else e) - r
             visited += 1
-            prev = t if (not tri or t - gbase >= 64) else None
+            prev = t if (not tri or t - gbase >= width) else None
             tn = t + 1
-            if not full and e <= wm.DEPTHS and (not tri or t - gbase >= 64):
+            if not full and e <= wm.DEPTHS and (not tri or t - gbase >= width):
                 tn = max(int(gend[t, e - 1]), t + 1)
                 skipped += min(tn, te) - t - 1
                 # every skipped text: no lane within k (full DP distances)
@@ -75,3 +76,17 @@ def test_traversal_totals_small():
     out = wm.traversal(synth.small(), 1, 16384, 1 << 20)
     assert out["exact"] and out["items"] == out["items_modelled"]
     assert 0 < out["visited_texts"] <= out["wave_steps"]
+
+
+def test_group_widths_follow_pattern_length():
+    """Two patterns share a lane for pattern lengths up to 16 (k < 16): the
+    items of a bucket pair cover its patterns in groups of 128, otherwise 64,
+    and every pattern lands in exactly one group per text chunk."""
+    s, L, order, gend, items = _setup(3000, 256, 1, 4)
+    Ls = L[order]
+    for gbase, npat, tb, te, tri, width in items.tolist():
+        m = int(Ls[gbase])
+        assert width == (128 if m <= wm.PACK_MAX_LEN else 64)
+        assert 1 <= npat <= width and (Ls[gbase:gbase + npat] == m).all()
+    assert wm.group_width(16, 15, True) == 128 and wm.group_width(16, 16, True) == 64
+    assert wm.group_width(17, 1, True) == 64 and wm.group_width(10, 1, False) == 64
