@@ -367,6 +367,9 @@ def main():
             "frac_of_measured": achieved / peak_meas if priced else None,
             "per_pair_work_lane_instr": pair_work,
             "traversal_saving": pair_work / work_instr,
+            # every kept pair priced at its own exit step, per second, over the
+            # peak: above 1 because the walk skips most of that work
+            "frac_pair_work": pair_work / (pk_ms * 1e-3) / PEAK_LANE_OPS,
         },
     }
     log("host-to-host build ...")

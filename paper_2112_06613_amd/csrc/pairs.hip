@@ -423,6 +423,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
   // stops after finding every stripe empty in a row
   uint32_t stripe = (blockIdx.x * (kBlock / kWave) + rfl(wid)) % kQueueStripes;
   uint32_t empty = 0;
+  uint32_t dcache = 0;  // descriptor of the wave's previous item
   for (;;) {
     uint64_t j = 0;
     if (lane == 0) j = atomicAdd(&cnt->queue[stripe].next, 1ull);
@@ -436,10 +437,16 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     empty = 0;
 
     // descriptor holding this item: largest di with item_base[di] <= item
-    uint32_t lo = 0, hi = nd;
-    while (hi - lo > 1) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (item_base[mid] <= item) lo = mid; else hi = mid;
+    // (usually the previous item's; otherwise a binary search)
+    uint32_t lo = dcache;
+    if (!(item_base[lo] <= item && (lo + 1 >= nd || item < item_base[lo + 1]))) {
+      lo = 0;
+      uint32_t hi = nd;
+      while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (item_base[mid] <= item) lo = mid; else hi = mid;
+      }
+      dcache = lo;
     }
     const Desc d = descs[lo];
     const uint32_t local = (uint32_t)(item - d.item_base);
