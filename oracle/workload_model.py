@@ -135,10 +135,17 @@ def group_width(m: int, k: int, pack: bool) -> int:
     return 2 * WAVE if pack and m <= PACK_MAX_LEN and k < 16 else WAVE
 
 
+def diag_texts(T: int) -> int:
+    """Texts per work item of a triangle row block's first T texts."""
+    return max(64, T // 8 // 64 * 64)
+
+
 def plan_items(L_sorted, k: int, T: int, pack: bool = True) -> np.ndarray:
     """The pair kernel's work items of a one-segment build: rows (gbase, np,
     tb, te, tri, width) over sorted positions; width = patterns per item
-    (64, or 128 when two patterns share a lane)."""
+    (64, or 128 when two patterns share a lane).  A triangle row block's
+    first T texts come in chunks of diag_texts(T) (an item there may be
+    empty: tb >= te), the rest in chunks of T."""
     cnt = np.bincount(L_sorted, minlength=34)
     off = np.concatenate([[0], np.cumsum(cnt)])
     rows = []
@@ -163,19 +170,26 @@ def plan_items(L_sorted, k: int, T: int, pack: bool = True) -> np.ndarray:
             else:
                 if npat < 2:
                     continue
+                # a row block's first T texts (its diagonal) in chunks of
+                # diag_texts(T), the rest in chunks of T
+                Td = diag_texts(T)
                 for bk in range((npat - 1 + T - 1) // T):
                     nrow = min(T, npat - bk * T)
                     p0 = off[m] + bk * T
                     ntb = npat - bk * T
                     g = np.arange((nrow + W - 1) // W)
-                    c = np.arange((ntb + T - 1) // T)
-                    G, C = np.meshgrid(g, c, indexing="ij")
-                    gb = p0 + W * G
-                    tb = p0 + T * C
-                    te = np.minimum(p0 + ntb, tb + T)
-                    tb = np.maximum(tb, gb + 1)
-                    npg = np.minimum(W, nrow - W * G)
-                    rows.append(np.stack([gb, npg, tb, te, np.ones_like(gb), np.full_like(gb, W)], -1).reshape(-1, 6))
+                    for t0, nt, Tc in ((p0, min(ntb, T), Td), (p0 + T, ntb - T, T)):
+                        if nt <= 0:
+                            continue
+                        c = np.arange((nt + Tc - 1) // Tc)
+                        G, C = np.meshgrid(g, c, indexing="ij")
+                        gb = p0 + W * G
+                        tb = t0 + Tc * C
+                        te = np.minimum(t0 + nt, tb + Tc)
+                        tb = np.maximum(tb, gb + 1)
+                        npg = np.minimum(W, nrow - W * G)
+                        rows.append(np.stack([gb, npg, tb, te, np.ones_like(gb), np.full_like(gb, W)],
+                                             -1).reshape(-1, 6))
     if not rows:
         return np.zeros((0, 6), dtype=np.uint32)
     return np.concatenate(rows).astype(np.uint32)

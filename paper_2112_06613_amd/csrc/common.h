@@ -60,6 +60,7 @@ struct alignas(16) Desc {
   uint32_t chunks;       // ceil(nt / texts_per_item)
   uint32_t pack;         // patterns per lane: 2 (m <= kPackMaxLen) or 1;
                          // a group is 64 * pack patterns
+  uint32_t T;            // texts per chunk
   uint64_t item_base;    // first item of this descriptor
   uint64_t items;        // groups * chunks
 };

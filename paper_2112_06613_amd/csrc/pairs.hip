@@ -152,7 +152,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
                                                   const uint64_t* __restrict__ item_base,
                                                   const Plan* __restrict__ plan, Counters* __restrict__ cnt,
                                                   uint32_t* __restrict__ edges, uint8_t* __restrict__ edist,
-                                                  uint64_t capacity, uint32_t T, int k) {
+                                                  uint64_t capacity, int k) {
   __shared__ uint32_t lds_eq[kPeqLds ? (kBlock / kWave) * kAlpha * kWave : 1];
   // per-wave edge staging: hits collect here and take their global slots
   // with one atomic per kEdgeBuf edges instead of one per hitting text
@@ -200,6 +200,11 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     const bool ok1 = kPack == 2 && g * kGroup + kWave + lane < d.np;
     const uint32_t p0 = ok0 ? gbase + lane : d.p0;
     const uint32_t p1 = ok1 ? gbase + kWave + lane : d.p0;
+    const uint32_t tb0 = d.t0 + c * d.T;
+    const uint32_t te = min(d.t0 + d.nt, tb0 + d.T);
+    uint32_t tb = tb0;
+    if (d.tri && tb < gbase + 1) tb = gbase + 1;
+    if (tb >= te) return;  // a diagonal chunk wholly before the group's patterns
 
     uint32_t eq[kAlpha];
     {
@@ -234,10 +239,6 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
       z_item = ok0 ? (1u << delta) - 1u : ~0u;
       m_item = 1u << delta;
     }
-    const uint32_t tb0 = d.t0 + c * T;
-    const uint32_t te = min(d.t0 + d.nt, tb0 + T);
-    uint32_t tb = tb0;
-    if (d.tri && tb < gbase + 1) tb = gbase + 1;
     // in a triangle item, texts before tri_end still have patterns at or
     // after them in the item (those patterns are masked off)
     const uint32_t tri_end = d.tri ? gbase + kGroup : 0u;
@@ -471,7 +472,7 @@ uint32_t pair_grid_blocks(int device, uint32_t waves_per_simd) {
 void launch_pairs(const PairArgs& a, uint32_t grid_blocks, bool peq_lds, hipStream_t st) {
 #define TCR_LAUNCH(LDS, MODE)                                                                              \
   hipLaunchKernelGGL((k_pairs<LDS, MODE>), dim3(grid_blocks), dim3(kBlock), 0, st, a.descs, a.item_base, a.plan, \
-                     a.cnt, a.edges, a.edist, a.capacity, a.texts_per_item, a.k)
+                     a.cnt, a.edges, a.edist, a.capacity, a.k)
   const int mode = a.k == 1 ? 1 : (a.k == 2 ? 2 : 0);
   if (peq_lds) {
     if (mode == 1) TCR_LAUNCH(true, 1);

@@ -305,6 +305,47 @@ __device__ uint64_t block_excl_scan_u64(uint64_t v, uint64_t* sh, uint64_t& tota
   return r;
 }
 
+// Texts per work item of a triangle's diagonal chunk (its first texts_per_item
+// texts, where the patterns share their prefixes with the texts and the walk
+// goes deepest): an eighth of the rest.
+__device__ __forceinline__ uint32_t diag_texts(uint32_t T) { return max(64u, T / 8u / 64u * 64u); }
+
+// Descriptors and items of entry `en` in plan pass `pass`: pass 0 holds the
+// rectangles and each triangle row block's texts past its first T (chunks
+// of T); pass 1 the row blocks' first T texts (chunks of diag_texts(T)).
+// Work items are handed out in plan order, so the diagonal chunks -- the
+// most expensive items, cut 8 ways -- come last and fill the end of the
+// launch while the big items drain.
+__device__ void pass_counts(const Entry& en, int pass, uint32_t T, uint32_t& ndesc, uint64_t& items) {
+  ndesc = 0;
+  items = 0;
+  if (en.ndesc == 0) return;
+  const uint32_t G = 64u * en.pack;
+  if (!en.tri) {
+    if (pass == 0) {
+      ndesc = 1;
+      items = en.items;
+    }
+    return;
+  }
+  const uint32_t Td = diag_texts(T);
+  for (uint32_t bk = 0; bk < en.ndesc; ++bk) {
+    const uint32_t rows = min(T, en.np - bk * T);
+    const uint32_t cols = en.np - bk * T;
+    const uint64_t groups = (rows + G - 1) / G;
+    if (pass == 0) {
+      if (cols > T) {
+        ndesc += 1;
+        items += groups * ((cols - T + T - 1) / T);
+      }
+    } else {
+      const uint32_t nt = min(cols, T);
+      ndesc += 1;
+      items += groups * ((nt + Td - 1) / Td);
+    }
+  }
+}
+
 __global__ __launch_bounds__(kPlanThreads) void k_plan(const PlanPart* __restrict__ parts, uint32_t n_parts,
                                                        PlanPart inline_part, int k, uint32_t T,
                                                        uint32_t pack_ok, Desc* __restrict__ descs,
@@ -315,55 +356,71 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(const PlanPart* __restric
     parts = nullptr;
     n_parts = 1;
   }
+  const uint32_t Td = diag_texts(T);
   uint64_t run_desc = 0, run_items = 0, run_pairs = 0;
-  for (uint32_t pi = 0; pi < n_parts; ++pi) {
-    const PlanPart part = parts ? parts[pi] : inline_part;
-    const uint32_t n_entries = part_entries(part, k);
-    for (uint32_t e0 = 0; e0 < n_entries; e0 += kPlanThreads) {
-      const uint32_t e = e0 + threadIdx.x;
-      Entry en;
-      en.ndesc = 0;
-      en.items = 0;
-      en.pairs = 0;
-      if (e < n_entries) en = entry_shape(part, e, k, T, pack_ok);
-      uint64_t tot_d, tot_i, tot_p;
-      const uint64_t dpos = run_desc + block_excl_scan_u64(en.ndesc, sh, tot_d);
-      const uint64_t ipos = run_items + block_excl_scan_u64(en.items, sh, tot_i);
-      block_excl_scan_u64(en.pairs, sh, tot_p);
-      if (en.ndesc > 0 && dpos + en.ndesc <= max_desc) {
-        Desc d;
-        d.prec = en.prec;
-        d.ppeq = en.ppeq;
-        d.trec = en.trec;
-        d.m = en.m;
-        d.n = en.n;
-        d.tri = en.tri;
-        d.pack = en.pack;
-        if (!en.tri) {
-          d.p0 = en.p0; d.np = en.np; d.t0 = en.t0; d.nt = en.nt;
-          d.chunks = (en.nt + T - 1) / T;
-          d.item_base = ipos;
-          d.items = en.items;
-          descs[dpos] = d;
-          item_base[dpos] = ipos;
-        } else {
-          uint64_t ib = ipos;
-          for (uint32_t bk = 0; bk < en.ndesc; ++bk) {
-            const uint32_t rows = min(T, en.np - bk * T);
-            d.p0 = en.p0 + bk * T; d.np = rows;
-            d.t0 = en.p0 + bk * T; d.nt = en.np - bk * T;
-            d.chunks = (d.nt + T - 1) / T;
-            d.item_base = ib;
-            d.items = (uint64_t)((rows + 64u * en.pack - 1) / (64u * en.pack)) * d.chunks;
-            descs[dpos + bk] = d;
-            item_base[dpos + bk] = ib;
-            ib += d.items;
+  for (int pass = 0; pass < 2; ++pass) {
+    for (uint32_t pi = 0; pi < n_parts; ++pi) {
+      const PlanPart part = parts ? parts[pi] : inline_part;
+      const uint32_t n_entries = part_entries(part, k);
+      for (uint32_t e0 = 0; e0 < n_entries; e0 += kPlanThreads) {
+        const uint32_t e = e0 + threadIdx.x;
+        Entry en;
+        en.ndesc = 0;
+        en.items = 0;
+        en.pairs = 0;
+        if (e < n_entries) en = entry_shape(part, e, k, T, pack_ok);
+        uint32_t nd;
+        uint64_t ni;
+        pass_counts(en, pass, T, nd, ni);
+        uint64_t tot_d, tot_i, tot_p;
+        const uint64_t dpos = run_desc + block_excl_scan_u64(nd, sh, tot_d);
+        const uint64_t ipos = run_items + block_excl_scan_u64(ni, sh, tot_i);
+        block_excl_scan_u64(pass == 0 ? en.pairs : 0, sh, tot_p);
+        if (nd > 0 && dpos + nd <= max_desc) {
+          Desc d;
+          d.prec = en.prec;
+          d.ppeq = en.ppeq;
+          d.trec = en.trec;
+          d.m = en.m;
+          d.n = en.n;
+          d.tri = en.tri;
+          d.pack = en.pack;
+          const uint32_t G = 64u * en.pack;
+          if (!en.tri) {
+            d.p0 = en.p0; d.np = en.np; d.t0 = en.t0; d.nt = en.nt;
+            d.T = T;
+            d.chunks = (en.nt + T - 1) / T;
+            d.item_base = ipos;
+            d.items = ni;
+            descs[dpos] = d;
+            item_base[dpos] = ipos;
+          } else {
+            uint64_t ib = ipos;
+            uint32_t q = 0;
+            for (uint32_t bk = 0; bk < en.ndesc; ++bk) {
+              const uint32_t rows = min(T, en.np - bk * T);
+              const uint32_t cols = en.np - bk * T;
+              d.p0 = en.p0 + bk * T; d.np = rows;
+              if (pass == 0) {
+                if (cols <= T) continue;
+                d.t0 = en.p0 + bk * T + T; d.nt = cols - T; d.T = T;
+              } else {
+                d.t0 = en.p0 + bk * T; d.nt = min(cols, T); d.T = Td;
+              }
+              d.chunks = (d.nt + d.T - 1) / d.T;
+              d.item_base = ib;
+              d.items = (uint64_t)((rows + G - 1) / G) * d.chunks;
+              descs[dpos + q] = d;
+              item_base[dpos + q] = ib;
+              ib += d.items;
+              ++q;
+            }
           }
         }
+        run_desc += tot_d;
+        run_items += tot_i;
+        run_pairs += tot_p;
       }
-      run_desc += tot_d;
-      run_items += tot_i;
-      run_pairs += tot_p;
     }
   }
   if (threadIdx.x == 0) {
@@ -432,8 +489,9 @@ void launch_gather(const SeqRec* rec, const uint32_t* val, const uint64_t* skey,
 
 uint32_t plan_max_desc_self(uint32_t n_seg, int k, uint32_t T, uint64_t n) {
   // rectangles: one per (segment, m, delta>0); triangles: sum over buckets of
-  // ceil((np-1)/T) <= n/T + 32 per segment
-  uint64_t v = (uint64_t)n_seg * 32u * (uint32_t)(k + 1) + n / T + (uint64_t)n_seg * 32u + 1;
+  // ceil((np-1)/T) <= n/T + 32 per segment row blocks, each a diagonal and
+  // (when it has more than T texts) an off-diagonal descriptor
+  uint64_t v = (uint64_t)n_seg * 32u * (uint32_t)(k + 1) + 2 * (n / T + (uint64_t)n_seg * 32u) + 1;
   return (uint32_t)v;
 }
 

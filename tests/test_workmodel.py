@@ -90,3 +90,27 @@ def test_group_widths_follow_pattern_length():
         assert 1 <= npat <= width and (Ls[gbase:gbase + npat] == m).all()
     assert wm.group_width(16, 15, True) == 128 and wm.group_width(16, 16, True) == 64
     assert wm.group_width(17, 1, True) == 64 and wm.group_width(10, 1, False) == 64
+
+
+@pytest.mark.parametrize("T,pack", [(128, True), (256, False), (64, True)])
+def test_items_cover_every_kept_pair_once(T, pack):
+    """The modelled work items tile the length-filtered pair space: summed
+    over items, the (pattern, text) pairs they hold (pattern before text in
+    a triangle) equal the kept pairs of the length histogram, and no item
+    holds a pair twice (its patterns and texts are disjoint ranges)."""
+    s, L, order, gend, items = _setup(3000, T, 1, 7, pack)
+    Ls = L[order]
+    total = 0
+    for gbase, npat, tb, te, tri, width in items.tolist():
+        if te <= tb:
+            continue
+        if tri:
+            # pairs (p, t): gbase <= p < gbase + npat, tb <= t < te, p < t
+            for p in range(gbase, gbase + npat):
+                total += max(0, te - max(tb, p + 1))
+        else:
+            total += npat * (te - tb)
+        assert (Ls[tb:te] == Ls[tb]).all()
+    cnt = np.bincount(Ls, minlength=34).astype(np.int64)
+    want = sum(int(cnt[m] * (cnt[m] - 1) // 2 + cnt[m] * cnt[m - 1]) for m in range(2, 33)) + int(cnt[1] * (cnt[1] - 1) // 2)
+    assert total == want
