@@ -32,7 +32,7 @@ def _eq(g, e, d):
     assert np.array_equal(g.degree, d)
 
 
-@pytest.mark.parametrize("k", [0, 1, 2, 3, 5, 8, 31])
+@pytest.mark.parametrize("k", [0, 1, 2, 3, 5, 8, 15, 16, 31])
 def test_small_repertoire_matches_oracle(tn, ctx, orc, k):
     s = synth.small()
     g = tn.tcrnet_build(ctx, s, k)
@@ -167,7 +167,9 @@ def test_threshold_monotone(tn, ctx):
 
 
 @pytest.mark.parametrize("opts", [dict(texts_per_item=64), dict(texts_per_item=2048, waves_per_simd=2),
-                                  dict(flags=2), dict(flags=2, texts_per_item=192), dict(edge_capacity=16)])
+                                  dict(flags=2), dict(flags=2, texts_per_item=192), dict(edge_capacity=16),
+                                  dict(flags=4), dict(flags=4 | 2, texts_per_item=320),
+                                  dict(texts_per_item=576, waves_per_simd=3)])
 def test_schedules_give_identical_results(tn, orc, opts):
     s = synth.repertoire(5000, 500, 31)
     e, d = orc.build(s, 2)
