@@ -141,7 +141,7 @@ __device__ __forceinline__ bool within_k_lane(uint32_t z, int k) {
 }
 
 template <int V>
-struct PackTag {
+struct Tag {
   static constexpr int value = V;
 };
 
@@ -255,7 +255,14 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     uint32_t r = 0;
 
     uint32_t t = tb;
-    while (t < te) {
+    // The texts are walked in two runs, each with its own copy of the loop:
+    // first the ragged ones (in a triangle item, texts before tri_end, where
+    // the set of valid patterns still grows with the next texts, so neither
+    // jumps nor resumed state apply and later patterns are masked), then
+    // the rest, whose loop carries none of that per-text bookkeeping.
+    auto walk = [&](auto rag_tag, uint32_t t_end) {
+    constexpr bool kRagged = decltype(rag_tag)::value;
+    while (t < t_end) {
       // the whole record (codes, length, id, group ends): one scalar load
       const SeqRec tr = load_const_at<SeqRec>(tbase, (t - tb0) * (uint32_t)sizeof(SeqRec));
       uint32_t tn = t + 1;  // next text
@@ -263,12 +270,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
       // record's packed lengths): the steps the next text can reuse
       uint32_t lcp_next = 0;
       uint32_t z_text = z_item;
-      // ragged: the set of valid patterns still grows with the next texts,
-      // so neither jumps (tcap keeps them at the next text) nor resumed
-      // state apply
-      const bool ragged = t < tri_end;
-      const uint32_t tcap = ragged ? t + 1 : ~0u;
-      if (ragged) {  // patterns not before the text are masked
+      if constexpr (kRagged) {  // patterns not before the text are masked
         const uint32_t dt = t - gbase;
         if constexpr (kPack == 2) {
           if (lane >= dt) z_text |= 0xFFFFu;
@@ -350,8 +352,8 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
 #define TCR_CLOSE(J)                                                           \
     } else {                                                                   \
       ex = (J);                                                                \
-      if constexpr ((J) < kSkipDepths) {                                       \
-        tn = min(max(tr.nxt[(J)], t + 1), tcap);                               \
+      if constexpr ((J) < kSkipDepths && !kRagged) {                           \
+        tn = max(tr.nxt[(J)], t + 1);                                          \
         lcp_next = (J) == 0 ? 0u : (tr.len >> (10 + 3 * ((J) - 1))) & 7u;      \
       } else {                                                                 \
         lcp_next = (tr.len >> 6) & 15u;                                        \
@@ -408,7 +410,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
           staged += nh;
         }
       }
-      r = ragged ? 0u : min(lcp_next, (uint32_t)kDepth);
+      r = kRagged ? 0u : min(lcp_next, (uint32_t)kDepth);
       t = tn;
 #undef TCR_OPEN
 #undef TCR_CLOSE
@@ -417,6 +419,9 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
 #undef TCR_EQ
 #undef TCR_CODE
     }
+    };
+    if (d.tri) walk(Tag<1>{}, min(te, tri_end));
+    walk(Tag<0>{}, te);
     if (kPeqLds) __builtin_amdgcn_wave_barrier();
   };
 
@@ -453,8 +458,8 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     const uint32_t local = (uint32_t)(item - d.item_base);
     const uint32_t g = local / d.chunks;
     const uint32_t c = local - g * d.chunks;
-    if (d.pack == 2) run_item(PackTag<2>{}, d, g, c);
-    else run_item(PackTag<1>{}, d, g, c);
+    if (d.pack == 2) run_item(Tag<2>{}, d, g, c);
+    else run_item(Tag<1>{}, d, g, c);
   }
   if (staged) flush();
 }
