@@ -82,7 +82,7 @@ def sample_pairs(lengths: np.ndarray, k: int, n_samples: int, seed: int):
 
 
 ALPHABET = "ARNDCQEGHILKMFPSTWYV"
-SORT_RESIDUES = 11   # residues in the sort key of a one-segment build
+SORT_RESIDUES = 8    # residues in the sort key (as many as the prefix-group depths)
 DEPTHS = 8           # prefix depths with a group end
 RESUME = 6           # text steps a visited text can take over from the previous one
 WAVE = 64

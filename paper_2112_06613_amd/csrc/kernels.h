@@ -24,7 +24,7 @@ void launch_record_keys(const SeqRec* rec, uint32_t n, uint64_t* key, uint32_t* 
 // invalid sequence in cnt->err_first / err_code.  rec[i].id = (id_base + i) | id_tag.
 // seg_off may be NULL when n_seg == 1.  The key is
 //   segment << (6 + 5 * nres) | length << (5 * nres) | first nres residues,
-// with nres = (58 - seg_bits) / 5, so key_bits = seg_bits + 6 + 5 * nres.
+// with nres = min(8, (58 - seg_bits) / 5), so key_bits = seg_bits + 6 + 5 * nres.
 int encode_key_bits(uint32_t seg_bits);
 int encode_combo_shift(uint32_t seg_bits);
 void launch_encode(const char* d_data, const uint64_t* d_off, uint32_t n, const uint32_t* seg_off,

@@ -55,7 +55,18 @@ __global__ void k_unpack(const uint64_t* __restrict__ keys, uint64_t E_max,
     p.y = b;
     reinterpret_cast<uint2*>(pairs)[e] = p;
     if (deg) {
-      atomicAdd(&deg[a], 1);
+      // edges arrive sorted by a: one atomic per run of equal a in the wave
+      const uint32_t lane = threadIdx.x & 63u;
+      const uint32_t a_up = (uint32_t)__shfl_up((int)a, 1);
+      const bool head = lane == 0 || a_up != a;
+      const uint64_t heads = __ballot(head);
+      const uint64_t valid = __ballot(true);  // lanes with e < E (the rest left the loop)
+      if (head) {
+        const uint64_t after = lane == 63 ? 0ull : (heads & ~((2ull << lane) - 1ull));
+        const uint32_t end = after ? (uint32_t)__ffsll((long long)after) - 1u
+                                   : 64u - (uint32_t)__clzll((long long)valid);
+        atomicAdd(&deg[a], (int32_t)(end - lane));
+      }
       if (mode == 0) atomicAdd(&deg[b], 1);
     }
   }

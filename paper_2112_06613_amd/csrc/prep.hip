@@ -453,7 +453,14 @@ void launch_reset_work(Counters* c, hipStream_t st) {
   hipLaunchKernelGGL(k_reset_work, dim3(1), dim3(64), 0, st, c);
 }
 
-static int encode_nres(uint32_t seg_bits) { return (int)((58 - seg_bits) / 5); }
+// Residues in the sort key: as many as the prefix-group ends need (kSkipDepths)
+// -- sorting deeper only reorders texts inside a depth-8 group, which neither
+// the jumps nor the resumed steps look at -- and never more than fit 58 bits
+// beside the segment.
+static int encode_nres(uint32_t seg_bits) {
+  const int fit = (int)((58 - seg_bits) / 5);
+  return fit < kSkipDepths ? fit : kSkipDepths;
+}
 int encode_key_bits(uint32_t seg_bits) { return (int)seg_bits + 6 + 5 * encode_nres(seg_bits); }
 int encode_combo_shift(uint32_t seg_bits) { return 5 * encode_nres(seg_bits); }
 
