@@ -140,6 +140,13 @@ __device__ __forceinline__ bool within_k_lane(uint32_t z, int k) {
   }
 }
 
+// Where a text's step chain ended (wave-uniform): ex = the step after which
+// no lane was within k (32: every step ran), tn = the next text to visit,
+// lcp = the steps that text reuses.
+struct StepExit {
+  uint32_t ex, tn, lcp;
+};
+
 template <int V>
 struct Tag {
   static constexpr int value = V;
@@ -265,10 +272,6 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     while (t < t_end) {
       // the whole record (codes, length, id, group ends): one scalar load
       const SeqRec tr = load_const_at<SeqRec>(tbase, (t - tb0) * (uint32_t)sizeof(SeqRec));
-      uint32_t tn = t + 1;  // next text
-      // common prefix of this text with the next visited one (from the
-      // record's packed lengths): the steps the next text can reuse
-      uint32_t lcp_next = 0;
       uint32_t z_text = z_item;
       if constexpr (kRagged) {  // patterns not before the text are masked
         const uint32_t dt = t - gbase;
@@ -279,15 +282,11 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
           if (lane >= dt) z_text = ~0u;
         }
       }
-      // per-text copies the compiler cannot see through, so that the per-step
-      // length and resume tests are formed inside the loop instead of being
+      // per-text copy of the length the compiler cannot see through, so that
+      // the per-step length tests are formed inside the loop instead of being
       // hoisted into (spilled) registers
-      uint32_t nn = n, rr = r;
-      asm volatile("" : "+s"(nn), "+s"(rr));
-      uint32_t mJ = m_item << rr;  // diagonal row bit(s) of the first computed step
-      uint32_t ex = 32;            // text step after which no lane was within k (32: none)
-      bool alive = true;
-      uint32_t VP = Mm, VN = 0, Z = z_text;
+      uint32_t nn = n;
+      asm volatile("" : "+s"(nn));
 
 // One Myers/Hyyro text step on character J, then the miss accounting: OR the
 // diagonal row's miss bit into Z; alive: some lane still within k.
@@ -321,11 +320,13 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
 // plain scalar or VCC branch): step J runs only while J < n and some lane is
 // still within k; a wave with none left records the step in ex.  Steps below
 // kDepth take their input from stack slot J-1 (or the first column) and keep
-// their output in slot J, unless reused from the previous text (J < r).
+// their output in slot J, unless reused from the previous text (J < r): in
+// the copy of the chain entered at depth kStart, steps below kStart are
+// reused without a test and steps from kStart up to kNext - 2 test J >= r.
 #define TCR_OPEN(J)                                                            \
-  if ((uint32_t)(J) < nn) {                                                    \
+  if ((J) < kStart || (uint32_t)(J) < nn) {                                    \
     if constexpr ((J) < kDepth) {                                              \
-      if ((uint32_t)(J) >= rr) {                                               \
+      if ((J) >= kNext - 1 || ((J) >= kStart && (kRagged || (uint32_t)(J) >= rr))) { \
         if constexpr ((J) > 0) {                                               \
           VP = sVP[TCR_SLOT((J) - 1)];                                         \
           VN = sVN[TCR_SLOT((J) - 1)];                                         \
@@ -361,6 +362,30 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     }                                                                          \
   }
 
+      // The step chain exists in one copy per entry depth kStart, serving
+      // resume depths r in [kStart, kNext): the resumed steps of a text cost
+      // no tests, where testing each one again costs about 9 scalar and
+      // branch instructions.  Entry depths 0, 4, 5 and 6: each copy adds
+      // registers, and these four keep the kernel within 96 VGPRs (five waves
+      // per SIMD).  The exit state comes back by value, the (per-lane) miss
+      // word through a reference, so the uniform values stay in scalar
+      // registers.
+      uint32_t rr = r;
+      asm volatile("" : "+s"(rr));
+      uint32_t Z;  // the miss word after the last computed step
+      auto chain = [&](auto start_tag, auto next_tag, uint32_t& z_out) __attribute__((always_inline)) {
+      constexpr int kStart = decltype(start_tag)::value;
+      constexpr int kNext = decltype(next_tag)::value;
+      uint32_t tn = t + 1;  // next text
+      // common prefix of this text with the next visited one (from the
+      // record's packed lengths): the steps the next text can reuse
+      uint32_t lcp_next = 0;
+      uint32_t ex = 32;  // text step after which no lane was within k (32: none)
+      uint32_t mJ = m_item << (kRagged ? 0u : rr);  // diagonal row bit(s) of the first computed step
+      bool alive = true;
+      uint32_t VP = Mm, VN = 0;
+      uint32_t& Z = z_out;
+      Z = z_text;
       TCR_OPEN(0) TCR_OPEN(1) TCR_OPEN(2) TCR_OPEN(3) TCR_OPEN(4) TCR_OPEN(5) TCR_OPEN(6) TCR_OPEN(7)
       TCR_OPEN(8) TCR_OPEN(9) TCR_OPEN(10) TCR_OPEN(11) TCR_OPEN(12) TCR_OPEN(13) TCR_OPEN(14)
       TCR_OPEN(15) TCR_OPEN(16) TCR_OPEN(17) TCR_OPEN(18) TCR_OPEN(19) TCR_OPEN(20) TCR_OPEN(21)
@@ -372,6 +397,20 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
       TCR_CLOSE(13) TCR_CLOSE(12) TCR_CLOSE(11) TCR_CLOSE(10) TCR_CLOSE(9) TCR_CLOSE(8)
       TCR_CLOSE(7) TCR_CLOSE(6) TCR_CLOSE(5) TCR_CLOSE(4) TCR_CLOSE(3) TCR_CLOSE(2) TCR_CLOSE(1)
       TCR_CLOSE(0)
+      return StepExit{ex, tn, lcp_next};
+      };
+      static_assert(kDepth == 6, "the entry depths cover resume depths 0..6");
+      StepExit x;
+      if constexpr (kRagged) {
+        x = chain(Tag<0>{}, Tag<1>{}, Z);
+      } else {
+        if (rr < 4) x = chain(Tag<0>{}, Tag<4>{}, Z);
+        else if (rr < 5) x = chain(Tag<4>{}, Tag<5>{}, Z);
+        else if (rr < 6) x = chain(Tag<5>{}, Tag<6>{}, Z);
+        else x = chain(Tag<6>{}, Tag<7>{}, Z);
+      }
+      const uint32_t ex = x.ex, tn = x.tn;
+      uint32_t lcp_next = x.lcp;
 
       if (ex == 32) {
         lcp_next = (tr.len >> 6) & 15u;
