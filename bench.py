@@ -62,12 +62,12 @@ def source_sha1(files) -> str:
     return h.hexdigest()
 
 
-def counted_traffic(texts_per_item: int):
+def counted_traffic(texts_per_item: int, peq_lds: int):
     """HBM bytes per pair-kernel launch from the committed FETCH_SIZE /
     WRITE_SIZE counts (bench_traffic.json), each scaled by what the same
     counter reads for a device copy of known size; None once the kernel's
-    sources or the work-item size differ from those the counters were taken
-    with."""
+    sources, the work-item size or the kernel variant differ from those the
+    counters were taken with."""
     path = os.path.join(ROOT, "bench_traffic.json")
     if not os.path.exists(path):
         log("no HBM counter record: traffic not reported")
@@ -79,6 +79,9 @@ def counted_traffic(texts_per_item: int):
         return None
     if texts_per_item != rec["texts_per_item"]:
         log(f"HBM counters were taken at {rec['texts_per_item']} texts per item: traffic not reported")
+        return None
+    if peq_lds != rec["peq_lds"]:
+        log(f"HBM counters were taken with peq_lds={rec['peq_lds']}: traffic not reported")
         return None
     kib = 1024.0
     return (rec["fetch_kib"] * kib * rec["fetch_scale"] + rec["write_kib"] * kib * rec["write_scale"])
@@ -351,7 +354,7 @@ def main():
             "peak": PEAK_LANE_OPS / 1e12,
             "unit": "T lane-instr/s",
             "frac": achieved / PEAK_LANE_OPS if priced else None,
-            "traffic": counted_traffic(T_used),
+            "traffic": counted_traffic(T_used, infos[-1]["peq_lds"]),
             "traffic_unit": "B per launch",
             "kernel": "k_pairs",
             "work_per_unit": f"{WAVE} lanes x {T_STEP_INSTR} VALU instr per wave text step "

@@ -94,9 +94,12 @@ typedef struct {
 } tcrnet_opts;
 
 #define TCRNET_F_NO_AUTOTUNE 1u   /* never consult or run the autotuner */
-#define TCRNET_F_PEQ_LDS 2u       /* keep pattern bit masks in LDS instead of VGPRs */
+#define TCRNET_F_PEQ_LDS 2u       /* keep pattern bit masks in LDS (default for
+                                     builds of at least 2^19 sequences) */
 #define TCRNET_F_NO_PACK 4u       /* one pattern per lane also for patterns of <= 16
                                      residues (default: two, in 16-bit halves) */
+#define TCRNET_F_PEQ_VGPR 8u      /* keep pattern bit masks in VGPRs (default for
+                                     smaller builds and for serving) */
 
 /* Create a context on HIP device `device` (stream, workspace, options).
    Fails with TCRNET_EDEVICE if the device is absent or not gfx950. */

@@ -20,6 +20,7 @@ TCRNET_OK, TCRNET_EINVAL, TCRNET_ENOMEM, TCRNET_EDEVICE, TCRNET_ESTATE, TCRNET_E
 TCRNET_F_NO_AUTOTUNE = 1
 TCRNET_F_PEQ_LDS = 2
 TCRNET_F_NO_PACK = 4
+TCRNET_F_PEQ_VGPR = 8
 MAX_LEN = 32
 MAX_K = 31
 

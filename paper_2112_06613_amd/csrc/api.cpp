@@ -56,6 +56,12 @@ namespace tcr {
 
 Sched pick_sched(const tcrnet_ctx* ctx, uint64_t n, int k) {
   Sched s;
+  // Pattern masks in LDS leave the pair kernel 79 VGPRs (six waves per SIMD
+  // instead of five): faster once a launch keeps the chip full for most of
+  // its time (N = 800,000: 2.61 -> 2.50 ms at k = 1, 25.1 -> 23.4 ms at
+  // k = 2); below that the tail of partly filled SIMDs favours the masks in
+  // VGPRs, whose reads are off the LDS latency (N = 100,000: 0.62 vs 0.70 ms).
+  s.peq_lds = n >= kPeqLdsMinSeqs;
   if (!(ctx->opts.flags & TCRNET_F_NO_AUTOTUNE)) {
     auto it = ctx->tuned.find(std::make_pair((int)bits_for(n ? n : 1), k));
     if (it != ctx->tuned.end()) s = it->second;
@@ -63,6 +69,7 @@ Sched pick_sched(const tcrnet_ctx* ctx, uint64_t n, int k) {
   if (ctx->opts.texts_per_item) s.texts_per_item = ctx->opts.texts_per_item;
   if (ctx->opts.waves_per_simd) s.waves_per_simd = ctx->opts.waves_per_simd;
   if (ctx->opts.flags & TCRNET_F_PEQ_LDS) s.peq_lds = true;
+  if (ctx->opts.flags & TCRNET_F_PEQ_VGPR) s.peq_lds = false;
   if (ctx->opts.flags & TCRNET_F_NO_PACK) s.pack = false;
   // whole waves of 64 texts per item keep triangle items non-empty
   s.texts_per_item = std::max<uint32_t>(64, (s.texts_per_item + 63) / 64 * 64);
@@ -494,8 +501,8 @@ int32_t tcrnet_autotune(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k) {
     for (uint32_t W : Ws)
       for (bool L : Ls) {
         ctx->opts = saved;
-        ctx->opts.flags = (saved_flags | TCRNET_F_NO_AUTOTUNE) & ~TCRNET_F_PEQ_LDS;
-        if (L) ctx->opts.flags |= TCRNET_F_PEQ_LDS;
+        ctx->opts.flags = (saved_flags | TCRNET_F_NO_AUTOTUNE) & ~(TCRNET_F_PEQ_LDS | TCRNET_F_PEQ_VGPR);
+        ctx->opts.flags |= L ? TCRNET_F_PEQ_LDS : TCRNET_F_PEQ_VGPR;
         ctx->opts.texts_per_item = T;
         ctx->opts.waves_per_simd = W;
         PipeParams pp;

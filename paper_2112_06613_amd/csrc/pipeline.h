@@ -35,6 +35,9 @@ struct DevBuf {
 };
 
 // Pair-kernel schedule.
+// Builds of at least this many sequences keep pattern masks in LDS.
+constexpr uint64_t kPeqLdsMinSeqs = 1ull << 19;
+
 struct Sched {
   uint32_t texts_per_item = 16384;
   uint32_t waves_per_simd = 8;

@@ -609,6 +609,8 @@ int32_t tcrnet_index_create(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k_
   // waves busy on each request (measured best for 1-4,096 queries against
   // 800,000 resident sequences)
   if (!ctx->opts.texts_per_item) idx->sched.texts_per_item = 1024;
+  // and such launches run mostly in their tail: pattern masks in VGPRs
+  if (!(ctx->opts.flags & TCRNET_F_PEQ_LDS)) idx->sched.peq_lds = false;
   const uint32_t n_slots = ctx->opts.max_inflight ? ctx->opts.max_inflight : 4;
   idx->grid = pair_grid_blocks(ctx->device, idx->sched.waves_per_simd);  // upper bound per request
   size_t free_b = 0, total_b = 0;

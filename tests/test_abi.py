@@ -20,6 +20,17 @@ def test_exports_every_declared_symbol():
     assert not missing, missing
 
 
+def test_flag_constants_match_header():
+    import re
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    with open(os.path.join(root, "include", "tcrnet.h")) as f:
+        hdr = f.read()
+    flags = {m.group(1): int(m.group(2)) for m in re.finditer(r"#define (TCRNET_F_\w+) (\d+)u", hdr)}
+    assert set(flags) >= {"TCRNET_F_NO_AUTOTUNE", "TCRNET_F_PEQ_LDS", "TCRNET_F_NO_PACK", "TCRNET_F_PEQ_VGPR"}
+    for name, value in flags.items():
+        assert getattr(tn, name) == value, name
+
+
 def test_host_only_calls():
     lib = tn.load_library()
     assert lib.tcrnet_version().decode().startswith("tcrnet")

@@ -79,8 +79,14 @@ def test_medium_k2_sampled_rows_and_soundness(tn, ctx, orc):
 def test_paper_scale_k1_bit_exact(tn, ctx, orc):
     s = synth.paper_scale()
     g = tn.tcrnet_build(ctx, s, 1)
+    assert ctx.last_info()["peq_lds"] == 1  # the default at this size (2^19 or more)
     e, d = orc.k1_build(s)
     _eq(g, e, d)
+    # the same launch with the pattern masks in VGPRs
+    with tn.Context(0, flags=tn.TCRNET_F_PEQ_VGPR) as c:
+        gv = tn.tcrnet_build(c, s, 1)
+        assert c.last_info()["peq_lds"] == 0
+    _eq(gv, e, d)
     # DP oracle on sampled rows (full rows of 800,000 comparisons each)
     rng = np.random.default_rng(11)
     rows = rng.choice(s.n, 12, replace=False).tolist()
@@ -169,7 +175,8 @@ def test_threshold_monotone(tn, ctx):
 @pytest.mark.parametrize("opts", [dict(texts_per_item=64), dict(texts_per_item=2048, waves_per_simd=2),
                                   dict(flags=2), dict(flags=2, texts_per_item=192), dict(edge_capacity=16),
                                   dict(flags=4), dict(flags=4 | 2, texts_per_item=320),
-                                  dict(texts_per_item=576, waves_per_simd=3)])
+                                  dict(texts_per_item=576, waves_per_simd=3), dict(flags=8),
+                                  dict(flags=8 | 2), dict(flags=8 | 4, texts_per_item=128)])
 def test_schedules_give_identical_results(tn, orc, opts):
     s = synth.repertoire(5000, 500, 31)
     e, d = orc.build(s, 2)
