@@ -81,7 +81,8 @@ typedef struct {
 /* Options; a zero field selects the default.  Pass NULL for all defaults. */
 typedef struct {
   uint32_t texts_per_item;  /* texts per work item of the pair kernel
-                               (0: autotuned table / 16384 for builds,
+                               (0: autotuned table / 16384 for builds of
+                               fewer than 2^19 sequences, 4096 from 2^19,
                                1024 for a serving index) */
   uint32_t waves_per_simd;  /* resident waves per SIMD of the persistent
                                pair kernel (0: 8) */

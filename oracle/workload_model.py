@@ -35,11 +35,13 @@ import synth
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 OUT = os.path.join(ROOT, "bench_model.json")
 
+# (generator, k, texts per work item: the library's default for the size,
+# 16384 below 2^19 sequences and 4096 from there)
 WORKLOADS = {
-    "small_n2000_k1": (synth.small, 1),
-    "medium_n50000_k1": (synth.medium, 1),
-    "medium_n50000_k2": (synth.medium, 2),
-    "paper_n800000_k1": (synth.paper_scale, 1),
+    "small_n2000_k1": (synth.small, 1, 16384),
+    "medium_n50000_k1": (synth.medium, 1, 16384),
+    "medium_n50000_k2": (synth.medium, 2, 16384),
+    "paper_n800000_k1": (synth.paper_scale, 1, 4096),
 }
 
 
@@ -249,8 +251,8 @@ def main():
     out = {"note": "written by oracle/workload_model.py; exit steps from the oracle's full DP table; "
                    "traversal = text steps of the sorted-text walk with prefix-group jumps",
            "workloads": {}}
-    for name, (gen, k) in WORKLOADS.items():
-        out["workloads"][name] = model(gen(), k, args.samples)
+    for name, (gen, k, T) in WORKLOADS.items():
+        out["workloads"][name] = model(gen(), k, args.samples, T=T)
         print(name, out["workloads"][name])
     with open(OUT, "w") as f:
         json.dump(out, f, indent=1, sort_keys=True)

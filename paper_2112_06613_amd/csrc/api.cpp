@@ -61,7 +61,10 @@ Sched pick_sched(const tcrnet_ctx* ctx, uint64_t n, int k) {
   // its time (N = 800,000: 2.61 -> 2.50 ms at k = 1, 25.1 -> 23.4 ms at
   // k = 2); below that the tail of partly filled SIMDs favours the masks in
   // VGPRs, whose reads are off the LDS latency (N = 100,000: 0.62 vs 0.70 ms).
+  // At those sizes 4,096 texts per work item end the launch with a shorter
+  // tail than 16,384 (2.52 -> 2.46 ms at k = 1, 23.5 -> 22.9 ms at k = 2).
   s.peq_lds = n >= kPeqLdsMinSeqs;
+  if (s.peq_lds) s.texts_per_item = kTextsPerItemLarge;
   if (!(ctx->opts.flags & TCRNET_F_NO_AUTOTUNE)) {
     auto it = ctx->tuned.find(std::make_pair((int)bits_for(n ? n : 1), k));
     if (it != ctx->tuned.end()) s = it->second;

@@ -35,8 +35,10 @@ struct DevBuf {
 };
 
 // Pair-kernel schedule.
-// Builds of at least this many sequences keep pattern masks in LDS.
+// Builds of at least this many sequences keep pattern masks in LDS and take
+// shorter work items (texts per item).
 constexpr uint64_t kPeqLdsMinSeqs = 1ull << 19;
+constexpr uint32_t kTextsPerItemLarge = 4096;
 
 struct Sched {
   uint32_t texts_per_item = 16384;
