@@ -255,10 +255,14 @@ __device__ Entry entry_shape(const PlanPart& part, uint32_t e, int k, uint32_t T
       if (r.np < 2) return r;
       r.tri = 1;
       r.ndesc = (r.np - 1 + T - 1) / T;  // row blocks b with b*T <= np-2
+      // row block bk: ceil(rows / G) groups (G a power of two) times
+      // ceil((np - bk*T) / T) = C - bk chunks (no division in the loop:
+      // one thread plans a whole triangle)
+      const uint32_t gsh = r.pack == 2 ? 7u : 6u;
+      const uint32_t C = (r.np + T - 1) / T;
       for (uint32_t bk = 0; bk < r.ndesc; ++bk) {
         const uint32_t rows = min(T, r.np - bk * T);
-        const uint32_t cols = r.np - bk * T;
-        r.items += (uint64_t)((rows + G - 1) / G) * ((cols + T - 1) / T);
+        r.items += (uint64_t)((rows + G - 1) >> gsh) * (C - bk);
       }
       r.pairs = (uint64_t)r.np * (r.np - 1) / 2;
     }
@@ -310,6 +314,27 @@ __device__ uint64_t block_excl_scan_u64(uint64_t v, uint64_t* sh, uint64_t& tota
 // goes deepest): an eighth of the rest.
 __device__ __forceinline__ uint32_t diag_texts(uint32_t T) { return max(64u, T / 8u / 64u * 64u); }
 
+// Text chunks of row block bk (patterns bk*T .. of a triangle over np sorted
+// sequences) in plan pass `pass`: pass 0, its texts past its first T in
+// chunks of T, ceil((np - bk*T - T) / T) = C - bk - 1; pass 1, its first
+// min(np - bk*T, T) texts in chunks of Td: cT for a whole block, cr for the
+// block of np mod T.  The divisions are taken once per triangle (one
+// thread plans all of a triangle's row blocks).
+struct TriChunks {
+  uint32_t C, cT, cr;
+};
+__device__ __forceinline__ TriChunks tri_shape(uint32_t np, uint32_t T, uint32_t Td) {
+  TriChunks c;
+  c.C = (np + T - 1) / T;
+  c.cT = (T + Td - 1) / Td;
+  c.cr = (np % T + Td - 1) / Td;
+  return c;
+}
+__device__ __forceinline__ uint32_t tri_chunks(const TriChunks& c, uint32_t np, uint32_t bk, int pass, uint32_t T) {
+  if (pass == 0) return c.C - bk - 1;
+  return np - bk * T >= T ? c.cT : c.cr;
+}
+
 // Descriptors and items of entry `en` in plan pass `pass`: pass 0 holds the
 // rectangles and each triangle row block's texts past its first T (chunks
 // of T); pass 1 the row blocks' first T texts (chunks of diag_texts(T)).
@@ -329,19 +354,19 @@ __device__ void pass_counts(const Entry& en, int pass, uint32_t T, uint32_t& nde
     return;
   }
   const uint32_t Td = diag_texts(T);
+  const TriChunks tc = tri_shape(en.np, T, Td);
   for (uint32_t bk = 0; bk < en.ndesc; ++bk) {
     const uint32_t rows = min(T, en.np - bk * T);
     const uint32_t cols = en.np - bk * T;
-    const uint64_t groups = (rows + G - 1) / G;
+    const uint64_t groups = (rows + G - 1) >> (en.pack == 2 ? 7u : 6u);
     if (pass == 0) {
       if (cols > T) {
         ndesc += 1;
-        items += groups * ((cols - T + T - 1) / T);
+        items += groups * tri_chunks(tc, en.np, bk, 0, T);
       }
     } else {
-      const uint32_t nt = min(cols, T);
       ndesc += 1;
-      items += groups * ((nt + Td - 1) / Td);
+      items += groups * tri_chunks(tc, en.np, bk, 1, T);
     }
   }
 }
@@ -397,6 +422,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(const PlanPart* __restric
           } else {
             uint64_t ib = ipos;
             uint32_t q = 0;
+            const TriChunks tc = tri_shape(en.np, T, Td);
             for (uint32_t bk = 0; bk < en.ndesc; ++bk) {
               const uint32_t rows = min(T, en.np - bk * T);
               const uint32_t cols = en.np - bk * T;
@@ -407,9 +433,9 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(const PlanPart* __restric
               } else {
                 d.t0 = en.p0 + bk * T; d.nt = min(cols, T); d.T = Td;
               }
-              d.chunks = (d.nt + d.T - 1) / d.T;
+              d.chunks = tri_chunks(tc, en.np, bk, pass, T);
               d.item_base = ib;
-              d.items = (uint64_t)((rows + G - 1) / G) * d.chunks;
+              d.items = (uint64_t)((rows + G - 1) >> (en.pack == 2 ? 7u : 6u)) * d.chunks;
               descs[dpos + q] = d;
               item_base[dpos + q] = ib;
               ib += d.items;
