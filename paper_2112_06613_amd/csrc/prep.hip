@@ -19,6 +19,29 @@ struct CodeTable {
 };
 __constant__ CodeTable kCodes = CodeTable();
 
+// The same codes for the letters 'A' + u, u < 26, as 5-bit fields of three
+// words (12 letters each; 31: not a residue), so a lane maps a byte with
+// register arithmetic instead of a per-lane table read.
+struct LetterCodes {
+  uint64_t w[3];
+  constexpr LetterCodes() : w() {
+    const CodeTable t;
+    for (int u = 0; u < 26; ++u) {
+      const int c = t.v['A' + u];
+      w[u / 12] |= (uint64_t)(c < 0 ? 31 : c) << (5 * (u % 12));
+    }
+  }
+};
+constexpr LetterCodes kLetters = LetterCodes();
+
+__device__ __forceinline__ int residue_code(uint32_t byte) {
+  const uint32_t u = byte - (uint32_t)'A';
+  if (u >= 26u) return -1;
+  const uint64_t word = u < 12u ? kLetters.w[0] : u < 24u ? kLetters.w[1] : kLetters.w[2];
+  const uint32_t c = (uint32_t)(word >> (5u * (u % 12u))) & 31u;
+  return c == 31u ? -1 : (int)c;
+}
+
 __global__ void k_fill_u32(uint32_t* p, uint64_t n, uint32_t v) {
   uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
   uint64_t stride = (uint64_t)gridDim.x * blockDim.x;
@@ -72,16 +95,31 @@ __global__ void k_encode(const char* __restrict__ data, const uint64_t* __restri
   }
   uint32_t w[6] = {0, 0, 0, 0, 0, 0};
   uint64_t lex = 0;
+  if (err != 2) {
+    // the string's bytes as the aligned dwords that hold them (at most 9 for
+    // 32 bytes; a dword holding a byte of the buffer lies in the same page)
+    const uintptr_t a0 = (uintptr_t)(data + b) & ~(uintptr_t)3;
+    const uint32_t lead = (uint32_t)((uintptr_t)(data + b) - a0);
+    const uint32_t nw = (lead + len + 3) / 4;
+    const __attribute__((address_space(1))) uint32_t* src =
+        reinterpret_cast<const __attribute__((address_space(1))) uint32_t*>(a0);
+    uint32_t dw[9];
 #pragma unroll
-  for (int q = 0; q < kMaxLen; ++q) {
-    if (q < (int)len && err != 2) {
-      int c = kCodes.v[(unsigned char)data[b + q]];
-      if (c < 0) {
-        if (err == 0) err = 1;
-        c = 0;
+    for (int j = 0; j < 9; ++j) dw[j] = (uint32_t)j < nw ? src[j] : 0u;
+    uint32_t al[8];  // the string's bytes 4j .. 4j+3
+#pragma unroll
+    for (int j = 0; j < 8; ++j) al[j] = __builtin_amdgcn_alignbit(dw[j + 1], dw[j], 8u * lead);
+#pragma unroll
+    for (int q = 0; q < kMaxLen; ++q) {
+      if (q < (int)len) {
+        int c = residue_code((al[q / 4] >> (8 * (q % 4))) & 255u);
+        if (c < 0) {
+          if (err == 0) err = 1;
+          c = 0;
+        }
+        w[q / 6] |= (uint32_t)c << (5 * (q % 6));
+        if (q < nres) lex |= (uint64_t)c << (5 * (nres - 1 - q));
       }
-      w[q / 6] |= (uint32_t)c << (5 * (q % 6));
-      if (q < nres) lex |= (uint64_t)c << (5 * (nres - 1 - q));
     }
   }
   uint32_t seg = 0;
