@@ -366,10 +366,10 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
       // resume depths r in [kStart, kNext): the resumed steps of a text cost
       // no tests, where testing each one again costs about 9 scalar and
       // branch instructions.  Entry depths 0, 4, 5 and 6: each copy adds
-      // registers, and these four keep the kernel within 96 VGPRs (five waves
-      // per SIMD).  The exit state comes back by value, the (per-lane) miss
-      // word through a reference, so the uniform values stay in scalar
-      // registers.
+      // registers, and these four keep the kernel within 96 VGPRs with the
+      // masks in VGPRs (five waves per SIMD) and within 80 with them in LDS
+      // (six).  The exit state comes back by value, the (per-lane) miss word
+      // through a reference, so the uniform values stay in scalar registers.
       uint32_t rr = r;
       asm volatile("" : "+s"(rr));
       uint32_t Z;  // the miss word after the last computed step
