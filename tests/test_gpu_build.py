@@ -186,7 +186,10 @@ def test_schedules_give_identical_results(tn, orc, opts):
 
 
 @pytest.mark.parametrize("bad,msg", [(["CASSF", "CAXSF"], "sequence 1"), (["CASSF", ""], "sequence 1"),
-                                     (["C" * 33], "sequence 0"), (["cassf"], "sequence 0")])
+                                     (["C" * 33], "sequence 0"), (["cassf"], "sequence 0"),
+                                     (["CASSF", "CASBF"], "sequence 1"), (["CASSF", "CASSZ"], "sequence 1"),
+                                     (["C@SSF"], "sequence 0"), (["CASS["], "sequence 0"),
+                                     (["CASSF", "CASSF", "CASJF", "CAOSF"], "sequence 2")])
 def test_invalid_input_rejected(tn, ctx, bad, msg):
     with pytest.raises(tn.TcrnetError) as ei:
         tn.tcrnet_build(ctx, bad, 1)
@@ -228,6 +231,28 @@ def test_device_entry_point_matches_host(tn, ctx):
     assert tn.tcrnet_build_device(ctx, chars, offs, 1, exact, deg) == E
     torch.cuda.synchronize()
     assert np.array_equal(exact.cpu().numpy().view(np.uint32), ref.pairs)
+    assert np.array_equal(deg.cpu().numpy(), ref.degree)
+
+
+@pytest.mark.parametrize("shift", [1, 2, 3])
+def test_device_entry_point_unaligned_chars(tn, ctx, shift):
+    # the strings start 1-3 bytes past an aligned address and the last one
+    # ends at the end of the buffer the caller passes
+    import torch
+    s = synth.repertoire(5000, 500, 41)
+    ref = tn.tcrnet_build(ctx, s, 1)
+    dev = torch.device("cuda", 0)
+    buf = torch.zeros(len(s.chars) + shift, dtype=torch.uint8, device=dev)
+    buf[shift:] = torch.from_numpy(s.chars).to(dev)
+    chars = buf[shift:]
+    assert chars.data_ptr() % 4 == shift
+    offs = torch.from_numpy(s.offsets.astype(np.int64)).to(dev)
+    deg = torch.empty(s.n, dtype=torch.int32, device=dev)
+    pairs = torch.empty((len(ref.pairs) + 1, 2), dtype=torch.int32, device=dev)
+    E = tn.tcrnet_build_device(ctx, chars, offs, 1, pairs, deg, torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    assert E == len(ref.pairs)
+    assert np.array_equal(pairs[:E].cpu().numpy().view(np.uint32), ref.pairs)
     assert np.array_equal(deg.cpu().numpy(), ref.degree)
 
 
