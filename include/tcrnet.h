@@ -81,9 +81,10 @@ typedef struct {
 /* Options; a zero field selects the default.  Pass NULL for all defaults. */
 typedef struct {
   uint32_t texts_per_item;  /* texts per work item of the pair kernel
-                               (0: autotuned table / 16384 for builds of
-                               fewer than 2^19 sequences, 4096 from 2^19,
-                               1024 for a serving index) */
+                               (0: autotuned table / about N/195 rounded
+                               down to a power of two in 512..16384, N the
+                               sequences of the launch; 1024 for a serving
+                               index) */
   uint32_t waves_per_simd;  /* resident waves per SIMD of the persistent
                                pair kernel (0: 8) */
   uint64_t edge_capacity;   /* initial edge buffer capacity in edges (0: sized
@@ -96,7 +97,7 @@ typedef struct {
 
 #define TCRNET_F_NO_AUTOTUNE 1u   /* never consult or run the autotuner */
 #define TCRNET_F_PEQ_LDS 2u       /* keep pattern bit masks in LDS (default for
-                                     builds of at least 2^19 sequences) */
+                                     builds of at least 2^18 sequences) */
 #define TCRNET_F_NO_PACK 4u       /* one pattern per lane also for patterns of <= 16
                                      residues (default: two, in 16-bit halves) */
 #define TCRNET_F_PEQ_VGPR 8u      /* keep pattern bit masks in VGPRs (default for

@@ -36,11 +36,11 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 OUT = os.path.join(ROOT, "bench_model.json")
 
 # (generator, k, texts per work item: the library's default for the size,
-# 16384 below 2^19 sequences and 4096 from there)
+# about n / 195 rounded down to a power of two in 512..16384)
 WORKLOADS = {
-    "small_n2000_k1": (synth.small, 1, 16384),
-    "medium_n50000_k1": (synth.medium, 1, 16384),
-    "medium_n50000_k2": (synth.medium, 2, 16384),
+    "small_n2000_k1": (synth.small, 1, 512),
+    "medium_n50000_k1": (synth.medium, 1, 512),
+    "medium_n50000_k2": (synth.medium, 2, 512),
     "paper_n800000_k1": (synth.paper_scale, 1, 4096),
 }
 

@@ -54,17 +54,18 @@ uint64_t default_capacity(const tcrnet_ctx* ctx, uint64_t n) {
 
 namespace tcr {
 
-Sched pick_sched(const tcrnet_ctx* ctx, uint64_t n, int k) {
+Sched pick_sched(const tcrnet_ctx* ctx, uint64_t n, int k, uint64_t n_set) {
   Sched s;
   // Pattern masks in LDS leave the pair kernel 79 VGPRs (six waves per SIMD
   // instead of five): faster once a launch keeps the chip full for most of
   // its time (N = 800,000: 2.61 -> 2.50 ms at k = 1, 25.1 -> 23.4 ms at
-  // k = 2); below that the tail of partly filled SIMDs favours the masks in
-  // VGPRs, whose reads are off the LDS latency (N = 100,000: 0.62 vs 0.70 ms).
-  // At those sizes 4,096 texts per work item end the launch with a shorter
-  // tail than 16,384 (2.52 -> 2.46 ms at k = 1, 23.5 -> 22.9 ms at k = 2).
+  // k = 2; N = 300,000: 5.75 -> 5.41 ms at k = 2); below that the tail of
+  // partly filled SIMDs favours the masks in VGPRs, whose reads are off the
+  // LDS latency.  Work items shrink with the set (default_texts_per_item):
+  // the tail of a launch is then shorter (N = 50,000, k = 2: 1.78 ms at
+  // 16,384 texts per item, 0.49 ms at 512).
   s.peq_lds = n >= kPeqLdsMinSeqs;
-  if (s.peq_lds) s.texts_per_item = kTextsPerItemLarge;
+  s.texts_per_item = default_texts_per_item(n_set ? n_set : n);
   if (!(ctx->opts.flags & TCRNET_F_NO_AUTOTUNE)) {
     auto it = ctx->tuned.find(std::make_pair((int)bits_for(n ? n : 1), k));
     if (it != ctx->tuned.end()) s = it->second;
@@ -384,6 +385,9 @@ int32_t tcrnet_build_batch(tcrnet_ctx* ctx, const tcrnet_seqs* reps, uint32_t n_
   pp.k = k;
   pp.capacity = default_capacity(ctx, n);
   pp.d_deg = ctx->out_deg.as<int32_t>();
+  // one launch over all repertoires: its work items are sized for the whole
+  // launch (256 repertoires of 1,000-40,000 sequences, 2.75 M in all: 21.1 ms
+  // at 8,192 texts per item, 21.9 ms at 512)
   Sched sched = pick_sched(ctx, n, k);
   pp.sched = sched;
   tcrnet_build_info info{};

@@ -35,10 +35,18 @@ struct DevBuf {
 };
 
 // Pair-kernel schedule.
-// Builds of at least this many sequences keep pattern masks in LDS and take
-// shorter work items (texts per item).
-constexpr uint64_t kPeqLdsMinSeqs = 1ull << 19;
-constexpr uint32_t kTextsPerItemLarge = 4096;
+// Builds over at least this many sequences keep pattern masks in LDS.
+constexpr uint64_t kPeqLdsMinSeqs = 1ull << 18;
+
+// Default texts per work item for a set of n sequences: about n / 195,
+// rounded down to a power of two in [512, 16384] (measured best at 50,000 to
+// 800,000 sequences: 512 up to 100,000, 1,024 at 200,000-300,000, 2,048 at
+// 400,000, 4,096 at 800,000).
+inline uint32_t default_texts_per_item(uint64_t n) {
+  uint32_t t = 512;
+  while (t < 16384 && (uint64_t)(2 * t) * 195 <= n) t *= 2;
+  return t;
+}
 
 struct Sched {
   uint32_t texts_per_item = 16384;

@@ -79,7 +79,8 @@ def test_medium_k2_sampled_rows_and_soundness(tn, ctx, orc):
 def test_paper_scale_k1_bit_exact(tn, ctx, orc):
     s = synth.paper_scale()
     g = tn.tcrnet_build(ctx, s, 1)
-    assert ctx.last_info()["peq_lds"] == 1  # the default at this size (2^19 or more)
+    info = ctx.last_info()  # the defaults at this size: masks in LDS, 4,096 texts per item
+    assert info["peq_lds"] == 1 and info["texts_per_item"] == 4096
     e, d = orc.k1_build(s)
     _eq(g, e, d)
     # the same launch with the pattern masks in VGPRs
