@@ -54,18 +54,18 @@ uint64_t default_capacity(const tcrnet_ctx* ctx, uint64_t n) {
 
 namespace tcr {
 
-Sched pick_sched(const tcrnet_ctx* ctx, uint64_t n, int k, uint64_t n_set) {
+Sched pick_sched(const tcrnet_ctx* ctx, uint64_t n, int k) {
   Sched s;
   // Pattern masks in LDS leave the pair kernel 79 VGPRs (six waves per SIMD
   // instead of five): faster once a launch keeps the chip full for most of
   // its time (N = 800,000: 2.61 -> 2.50 ms at k = 1, 25.1 -> 23.4 ms at
   // k = 2; N = 300,000: 5.75 -> 5.41 ms at k = 2); below that the tail of
   // partly filled SIMDs favours the masks in VGPRs, whose reads are off the
-  // LDS latency.  Work items shrink with the set (default_texts_per_item):
-  // the tail of a launch is then shorter (N = 50,000, k = 2: 1.78 ms at
-  // 16,384 texts per item, 0.49 ms at 512).
+  // LDS latency.  Work items shrink with the launch (default_texts_per_item):
+  // its tail is then shorter (N = 50,000, k = 2: 1.78 ms at 16,384 texts per
+  // item, 0.49 ms at 512).
   s.peq_lds = n >= kPeqLdsMinSeqs;
-  s.texts_per_item = default_texts_per_item(n_set ? n_set : n);
+  s.texts_per_item = default_texts_per_item(n);
   if (!(ctx->opts.flags & TCRNET_F_NO_AUTOTUNE)) {
     auto it = ctx->tuned.find(std::make_pair((int)bits_for(n ? n : 1), k));
     if (it != ctx->tuned.end()) s = it->second;

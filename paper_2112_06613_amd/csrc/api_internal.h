@@ -46,9 +46,8 @@ struct tcrnet_ctx {
 
 namespace tcr {
 
-// Schedule of a launch over n sequences (n_set: sequences of one independent
-// set, e.g. one repertoire of a batch; 0: n).
-Sched pick_sched(const tcrnet_ctx* ctx, uint64_t n, int k, uint64_t n_set = 0);
+// Schedule of a launch over n sequences.
+Sched pick_sched(const tcrnet_ctx* ctx, uint64_t n, int k);
 int32_t run_pipeline(tcrnet_ctx* ctx, Pipeline& pl, PipeParams pp, hipStream_t st, bool grow_ok,
                      DevBuf* pairs_buf, uint64_t* E, tcrnet_build_info* info, DevBuf* dist_buf = nullptr);
 

@@ -34,11 +34,10 @@ struct DevBuf {
   T* as() const { return static_cast<T*>(p); }
 };
 
-// Pair-kernel schedule.
 // Builds over at least this many sequences keep pattern masks in LDS.
 constexpr uint64_t kPeqLdsMinSeqs = 1ull << 18;
 
-// Default texts per work item for a set of n sequences: about n / 195,
+// Default texts per work item for a launch over n sequences: about n / 195,
 // rounded down to a power of two in [512, 16384] (measured best at 50,000 to
 // 800,000 sequences: 512 up to 100,000, 1,024 at 200,000-300,000, 2,048 at
 // 400,000, 4,096 at 800,000).
@@ -48,6 +47,7 @@ inline uint32_t default_texts_per_item(uint64_t n) {
   return t;
 }
 
+// Pair-kernel schedule.
 struct Sched {
   uint32_t texts_per_item = 16384;
   uint32_t waves_per_simd = 8;
