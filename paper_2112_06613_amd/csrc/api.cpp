@@ -114,9 +114,9 @@ int32_t run_pipeline(tcrnet_ctx* ctx, Pipeline& pl, PipeParams pp, hipStream_t s
     (void)hipEventRecord(ctx->ev_b0, st);
     pipeline_enqueue(pl, pp, ctx->device, st, ctx->ev_p0, ctx->ev_p1);
     (void)hipEventRecord(ctx->ev_b1, st);
-    Meta m;
-    e = pipeline_meta(pl, &m, st);
+    e = pipeline_meta(pl, ctx->h_meta, st);
     if (e != hipSuccess) return hip_error(e, "build");
+    const Meta m = *ctx->h_meta;
     float pk = 0.f, bt = 0.f;
     (void)hipEventElapsedTime(&pk, ctx->ev_p0, ctx->ev_p1);
     (void)hipEventElapsedTime(&bt, ctx->ev_b0, ctx->ev_b1);
@@ -165,6 +165,11 @@ int32_t tcrnet_ctx_create(int32_t device, const tcrnet_opts* opts, tcrnet_ctx** 
   (void)hipEventCreate(&c->ev_p1);
   (void)hipEventCreate(&c->ev_b0);
   (void)hipEventCreate(&c->ev_b1);
+  if ((e = hipHostMalloc((void**)&c->h_meta, sizeof(Meta), hipHostMallocDefault)) != hipSuccess) {
+    c->h_meta = nullptr;
+    (void)tcrnet_ctx_destroy(c);
+    return hip_error(e, "pinned host allocation");
+  }
   *out = c;
   return TCRNET_OK;
 }
@@ -178,6 +183,7 @@ int32_t tcrnet_ctx_destroy(tcrnet_ctx* ctx) {
   (void)hipEventDestroy(ctx->ev_p1);
   (void)hipEventDestroy(ctx->ev_b0);
   (void)hipEventDestroy(ctx->ev_b1);
+  if (ctx->h_meta) (void)hipHostFree(ctx->h_meta);
   (void)hipStreamDestroy(ctx->stream);
   delete ctx;
   return TCRNET_OK;
@@ -428,8 +434,8 @@ int32_t tcrnet_build_batch(tcrnet_ctx* ctx, const tcrnet_seqs* reps, uint32_t n_
       (void)hipEventRecord(ctx->ev_b0, ctx->stream);
       if ((e = hipGraphLaunch(ctx->batch_exec, ctx->stream)) != hipSuccess) return hip_error(e, "graph launch");
       (void)hipEventRecord(ctx->ev_b1, ctx->stream);
-      Meta m;
-      if ((e = pipeline_meta(ctx->pipe, &m, ctx->stream)) != hipSuccess) return hip_error(e, "batch build");
+      if ((e = pipeline_meta(ctx->pipe, ctx->h_meta, ctx->stream)) != hipSuccess) return hip_error(e, "batch build");
+      const Meta m = *ctx->h_meta;
       float bt = 0.f;
       (void)hipEventElapsedTime(&bt, ctx->ev_b0, ctx->ev_b1);
       info.build_ms += bt;

@@ -36,6 +36,7 @@ struct tcrnet_ctx {
   tcr::DevBuf in_data, in_off, in_seg, out_pairs, out_deg, out_dist;
   tcr::DevBuf ana_ws, ana_out;  // network-analysis workspace
   hipEvent_t ev_p0 = nullptr, ev_p1 = nullptr, ev_b0 = nullptr, ev_b1 = nullptr;
+  tcr::Meta* h_meta = nullptr;  // pinned host copy of a build's counters and plan
   std::map<std::pair<int, int>, tcr::Sched> tuned;  // (size class, k) -> schedule
   tcrnet_build_info last{};
   // batched build: captured launch sequence

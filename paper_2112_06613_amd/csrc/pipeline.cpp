@@ -174,9 +174,9 @@ void pipeline_enqueue(Pipeline& pl, const PipeParams& pp, int device, hipStream_
 }
 
 hipError_t pipeline_meta(const Pipeline& pl, Meta* host_meta, hipStream_t st) {
-  hipError_t e = hipMemcpyAsync(&host_meta->cnt, pl.cnt(), sizeof(Counters), hipMemcpyDeviceToHost, st);
-  if (e != hipSuccess) return e;
-  e = hipMemcpyAsync(&host_meta->plan, pl.plan(), sizeof(Plan), hipMemcpyDeviceToHost, st);
+  // the plan header follows the counters on the device as in Meta: one copy
+  static_assert(offsetof(Meta, plan) == sizeof(Counters), "Meta mirrors the device layout");
+  hipError_t e = hipMemcpyAsync(host_meta, pl.cnt(), sizeof(Counters) + sizeof(Plan), hipMemcpyDeviceToHost, st);
   if (e != hipSuccess) return e;
   return hipStreamSynchronize(st);
 }
