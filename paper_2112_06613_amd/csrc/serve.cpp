@@ -253,10 +253,9 @@ hipError_t enqueue_pairs(tcrnet_index* idx, Slot* s) {
   const int shift = (int)bits_for(ids > r->m ? ids : r->m);
   stage_canon(s->pl, r->insert ? 0 : 1, shift, s->capacity, s->d_pairs.as<uint32_t>(),
               r->insert ? nullptr : s->d_counts.as<int32_t>(), s->st);
-  Meta* hm = s->h_meta.as<Meta>();
-  if ((e = hipMemcpyAsync(&hm->cnt, s->pl.cnt(), sizeof(Counters), hipMemcpyDeviceToHost, s->st)) != hipSuccess)
-    return e;
-  if ((e = hipMemcpyAsync(&hm->plan, s->pl.plan(), sizeof(Plan), hipMemcpyDeviceToHost, s->st)) != hipSuccess)
+  // counters and plan header are adjacent on the device as in Meta: one copy
+  if ((e = hipMemcpyAsync(s->h_meta.as<Meta>(), s->pl.cnt(), sizeof(Counters) + sizeof(Plan),
+                          hipMemcpyDeviceToHost, s->st)) != hipSuccess)
     return e;
   (void)hipEventRecord(s->ev_meta, s->st);
   s->phase = 1;
