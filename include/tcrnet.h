@@ -114,6 +114,11 @@ TCRNET_API const char* tcrnet_last_error(void);
 TCRNET_API const char* tcrnet_status_string(int32_t status);
 /* Library version string. */
 TCRNET_API const char* tcrnet_version(void);
+/* Failure injection for tests of the error paths: after `after` more
+   successful device or pinned-host allocations made by the library (in any
+   thread), the next one fails as if the memory were exhausted (once); the
+   call then returns TCRNET_ENOMEM with no result.  after < 0 disarms. */
+TCRNET_API void tcrnet_debug_fail_alloc(int64_t after);
 
 /* ------------------------------------------------------------ plain build
  * The whole network of `seqs` at threshold k (paper, "TCR network" and
@@ -172,6 +177,10 @@ typedef struct {
   uint32_t waves_per_simd;
   uint32_t peq_lds;
   uint32_t pack;         /* 1: patterns of <= 16 residues ran two per lane */
+  uint32_t tuned;        /* 1: the schedule came from the autotuner */
+  uint32_t graph_captured; /* batched builds: 1 if this call captured a new
+                              HIP graph (first call, or a changed shape or
+                              buffer), 0 if it replayed the previous one */
 } tcrnet_build_info;
 TCRNET_API int32_t tcrnet_graph_info(const tcrnet_graph* g, tcrnet_build_info* info);
 /* Counters of the context's most recent build of any kind. */
@@ -179,11 +188,43 @@ TCRNET_API int32_t tcrnet_ctx_last_info(const tcrnet_ctx* ctx, tcrnet_build_info
 TCRNET_API void tcrnet_graph_free(tcrnet_graph* g);
 
 /* --------------------------------------------------------------- autotune
- * Time candidate pair-kernel schedules (texts per work item, waves per SIMD,
- * pattern masks in VGPRs or LDS) on `seqs` at threshold k and keep the
- * fastest in the context for inputs of the same size class and k.  Results
- * are exact for every candidate; only speed differs. */
+ * Time candidate pair-kernel schedules and keep the fastest in the context
+ * for later launches of the same form, size class (bits of the sequence
+ * count) and k.  Candidates: texts per work item 512 .. 16384 (powers of
+ * two) x resident waves per SIMD {4, 8} x pattern masks in VGPRs or LDS x
+ * two patterns per lane on or off (off only, with TCRNET_F_NO_PACK).  Each
+ * candidate is timed as the device time of its whole launch sequence, the
+ * fastest of two runs.  Results are exact for every candidate (the calls
+ * fail with TCRNET_EDEVICE if two candidates disagree on the edge count);
+ * only speed differs.  Explicit options (texts_per_item, waves_per_simd,
+ * TCRNET_F_PEQ_*) still override a tuned choice; TCRNET_F_NO_AUTOTUNE
+ * ignores the table.  The input is borrowed for the call. */
 TCRNET_API int32_t tcrnet_autotune(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k);
+/* The same for batched launches (tcrnet_build_batch): each candidate's
+ * launch sequence is captured as a HIP graph and replayed, and its time is
+ * that of a replay. */
+TCRNET_API int32_t tcrnet_autotune_batch(tcrnet_ctx* ctx, const tcrnet_seqs* reps, uint32_t n_reps, int32_t k);
+
+typedef struct {
+  uint32_t texts_per_item;
+  uint32_t waves_per_simd;
+  uint32_t peq_lds;
+  uint32_t pack;
+  double ms;  /* measured device time of the chosen schedule */
+} tcrnet_tune_entry;
+/* The tuned schedule for (form: batch = 1 or plain = 0, n sequences, k);
+   TCRNET_ESTATE if none. */
+TCRNET_API int32_t tcrnet_autotune_get(const tcrnet_ctx* ctx, int32_t batch, uint64_t n, int32_t k,
+                                       tcrnet_tune_entry* out);
+/* Persist the context's table as JSON (written to path + ".tmp", then
+   renamed); each entry names the device's arch (e.g. "gfx950") and CU
+   count, the form, size class and k, and the schedule. */
+TCRNET_API int32_t tcrnet_autotune_save(const tcrnet_ctx* ctx, const char* path);
+/* Merge the entries of a saved table that were measured on a device of the
+   same arch and CU count into the context's table; *n_loaded (may be NULL)
+   receives their number.  TCRNET_EINVAL for an unreadable or malformed file
+   (the context's table is then unchanged). */
+TCRNET_API int32_t tcrnet_autotune_load(tcrnet_ctx* ctx, const char* path, uint32_t* n_loaded);
 
 /* ------------------------------------------------------------- diagnostics
  * Measured 32-bit VALU issue rate of the context's device, in lane-
@@ -269,6 +310,16 @@ TCRNET_API int32_t tcrnet_components(tcrnet_ctx* ctx, const uint32_t* pairs, uin
    the size of the largest connected component of the rest. */
 TCRNET_API int32_t tcrnet_robustness(tcrnet_ctx* ctx, const uint32_t* pairs, uint64_t n_edges, uint32_t n,
                                      const uint32_t* order, const uint32_t* removed, uint32_t n_runs, uint32_t* lcc);
+
+/* Normalised LCC sizes of a percolation curve (paper, Methods, "Computing
+   LCC"): with p = removed[q] / n,
+     norm1[q] = LCC_norm,1(p) = lcc[q] / ((1 - p) n)   (0 when no node is left)
+     norm2[q] = LCC_norm,2(p) = LCC_norm,1(p) / LCC_norm,1(0)
+   (norm2 requires removed[0] = 0; if LCC_norm,1(0) = 0 it is norm1).
+   Host arrays of n_runs entries; norm1 or norm2 may be NULL.  TCRNET_EINVAL
+   if removed[q] > n or lcc[q] > n - removed[q].  Host arithmetic only. */
+TCRNET_API int32_t tcrnet_lcc_norm(const uint32_t* lcc, const uint32_t* removed, uint32_t n_runs, uint32_t n,
+                                   double* norm1, double* norm2);
 
 /* Degree statistics of a canonical edge list (i < j, sorted by (i, j),
    distinct: the output of the builds), paper, Methods, "Overview of network

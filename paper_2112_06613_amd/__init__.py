@@ -53,7 +53,7 @@ class tcrnet_build_info(ctypes.Structure):
                 ("build_ms", ctypes.c_double), ("pair_launches", ctypes.c_uint32),
                 ("texts_per_item", ctypes.c_uint32), ("waves_per_simd", ctypes.c_uint32),
                 ("peq_lds", ctypes.c_uint32),
-                ("pack", ctypes.c_uint32)]
+                ("pack", ctypes.c_uint32), ("tuned", ctypes.c_uint32), ("graph_captured", ctypes.c_uint32)]
 
 
 class tcrnet_result_info(ctypes.Structure):
@@ -74,6 +74,7 @@ _SIGS = [
     ("tcrnet_last_error", ctypes.c_char_p, []),
     ("tcrnet_status_string", ctypes.c_char_p, [_I32]),
     ("tcrnet_version", ctypes.c_char_p, []),
+    ("tcrnet_debug_fail_alloc", None, [ctypes.c_int64]),
     ("tcrnet_build", _I32, [_P, ctypes.POINTER(tcrnet_seqs), _I32, _PP]),
     ("tcrnet_build_device", _I32, [_P, _P, _P, ctypes.c_uint32, _I32, _P, _P, ctypes.c_uint64, _P, _U64P]),
     ("tcrnet_build_batch", _I32, [_P, ctypes.POINTER(tcrnet_seqs), ctypes.c_uint32, _I32, _PP]),
@@ -85,6 +86,10 @@ _SIGS = [
     ("tcrnet_build_weighted", _I32, [_P, ctypes.POINTER(tcrnet_seqs), _I32, _PP]),
     ("tcrnet_graph_distances", _I32, [_P, _PP, _U64P]),
     ("tcrnet_autotune", _I32, [_P, ctypes.POINTER(tcrnet_seqs), _I32]),
+    ("tcrnet_autotune_batch", _I32, [_P, ctypes.POINTER(tcrnet_seqs), ctypes.c_uint32, _I32]),
+    ("tcrnet_autotune_get", _I32, [_P, _I32, ctypes.c_uint64, _I32, ctypes.c_void_p]),
+    ("tcrnet_autotune_save", _I32, [_P, ctypes.c_char_p]),
+    ("tcrnet_autotune_load", _I32, [_P, ctypes.c_char_p, _U32P]),
     ("tcrnet_valu_peak", _I32, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
     ("tcrnet_index_create", _I32, [_P, ctypes.POINTER(tcrnet_seqs), _I32, _PP]),
     ("tcrnet_index_size", _I32, [_P, _U32P]),
@@ -297,6 +302,39 @@ def tcrnet_autotune(ctx: Context, seqs, k: int) -> None:
     _check(_lib.tcrnet_autotune(ctx.handle, ctypes.byref(s), k))
 
 
+class tcrnet_tune_entry(ctypes.Structure):
+    _fields_ = [("texts_per_item", ctypes.c_uint32), ("waves_per_simd", ctypes.c_uint32),
+                ("peq_lds", ctypes.c_uint32), ("pack", ctypes.c_uint32), ("ms", ctypes.c_double)]
+
+
+def tcrnet_autotune_batch(ctx: Context, reps, k: int) -> None:
+    conv = [_as_seqs(r) for r in reps]
+    arr = (tcrnet_seqs * max(1, len(conv)))()
+    for i, (c, o) in enumerate(conv):
+        arr[i] = _c_seqs(c, o)
+    _check(_lib.tcrnet_autotune_batch(ctx.handle, arr, len(conv), k))
+
+
+def tcrnet_autotune_get(ctx: Context, batch: bool, n: int, k: int) -> dict | None:
+    """The tuned schedule for (form, n, k), or None if there is none."""
+    e = tcrnet_tune_entry()
+    rc = _lib.tcrnet_autotune_get(ctx.handle, 1 if batch else 0, n, k, ctypes.byref(e))
+    if rc == TCRNET_ESTATE:
+        return None
+    _check(rc)
+    return {f: getattr(e, f) for f, _ in tcrnet_tune_entry._fields_}
+
+
+def tcrnet_autotune_save(ctx: Context, path: str) -> None:
+    _check(_lib.tcrnet_autotune_save(ctx.handle, os.fsencode(path)))
+
+
+def tcrnet_autotune_load(ctx: Context, path: str) -> int:
+    n = ctypes.c_uint32()
+    _check(_lib.tcrnet_autotune_load(ctx.handle, os.fsencode(path), ctypes.byref(n)))
+    return n.value
+
+
 def tcrnet_valu_peak(ctx: Context) -> tuple[float, float]:
     """Measured 32-bit VALU issue rate (lane-instructions/s) and the seconds
     the probe ran."""
@@ -427,6 +465,7 @@ _LATE = [
     ("tcrnet_robustness", _I32, [_P, _P, ctypes.c_uint64, ctypes.c_uint32, _P, _P, ctypes.c_uint32, _P]),
     ("tcrnet_graph_stats", _I32, [_P, _P, ctypes.c_uint64, ctypes.c_uint32, _P, _P, _P, ctypes.c_uint32, _P,
                                   ctypes.POINTER(tcrnet_stats)]),
+    ("tcrnet_lcc_norm", _I32, [_P, _P, ctypes.c_uint32, ctypes.c_uint32, _P, _P]),
 ]
 _SIGS += _LATE
 if _lib is not None:  # bound already: add the late signatures
@@ -462,19 +501,33 @@ def tcrnet_robustness(ctx: Context, pairs, n: int, order, removed) -> np.ndarray
     return out[:len(removed)]
 
 
+def tcrnet_lcc_norm(lcc, removed, n: int):
+    """(LCC_norm,1, LCC_norm,2) of a percolation curve (paper, "Computing
+    LCC"), computed by the library; removed[0] must be 0 for LCC_norm,2."""
+    lcc = np.ascontiguousarray(lcc, dtype=np.uint32)
+    removed = np.ascontiguousarray(removed, dtype=np.uint32)
+    m = len(lcc)
+    if len(removed) != m:
+        raise ValueError("lcc and removed differ in length")
+    n1 = np.zeros(max(1, m), dtype=np.float64)
+    n2 = np.zeros(max(1, m), dtype=np.float64)
+    want2 = m > 0 and removed[0] == 0
+    load_library()
+    _check(_lib.tcrnet_lcc_norm(lcc.ctypes.data, removed.ctypes.data, m, n, n1.ctypes.data,
+                                n2.ctypes.data if want2 else None))
+    return n1[:m], (n2[:m] if want2 else None)
+
+
 def lcc_norm1(lcc, removed, n: int) -> np.ndarray:
     """LCC(p) / ((1 - p) N) with p = removed / N (paper, "Computing LCC")."""
-    lcc = np.asarray(lcc, dtype=np.float64)
-    left = n - np.asarray(removed, dtype=np.float64)
-    return np.divide(lcc, left, out=np.zeros_like(lcc), where=left > 0)
+    return tcrnet_lcc_norm(lcc, removed, n)[0]
 
 
 def lcc_norm2(lcc, removed, n: int) -> np.ndarray:
     """LCC_norm,1(p) / LCC_norm,1(0); removed[0] must be 0."""
     if np.asarray(removed)[0] != 0:
         raise ValueError("removed[0] must be 0")
-    v = lcc_norm1(lcc, removed, n)
-    return v / v[0] if v[0] > 0 else v
+    return tcrnet_lcc_norm(lcc, removed, n)[1]
 
 
 def tcrnet_graph_stats(ctx: Context, pairs, n: int, hist_len: int = 0) -> dict:

@@ -155,4 +155,28 @@ int32_t tcrnet_graph_stats(tcrnet_ctx* ctx, const uint32_t* pairs, uint64_t n_ed
   return TCRNET_OK;
 }
 
+int32_t tcrnet_lcc_norm(const uint32_t* lcc, const uint32_t* removed, uint32_t n_runs, uint32_t n, double* norm1,
+                        double* norm2) {
+  if (n_runs && (!lcc || !removed)) return set_error(TCRNET_EINVAL, "NULL argument");
+  for (uint32_t q = 0; q < n_runs; ++q)
+    if (removed[q] > n || lcc[q] > n - removed[q])
+      return set_error(TCRNET_EINVAL, "run %u: removed or LCC size exceeds the nodes", q);
+  if (norm2 && n_runs && removed[0] != 0)
+    return set_error(TCRNET_EINVAL, "LCC_norm,2 needs removed[0] = 0 (the intact network)");
+  // LCC_norm,1(p) = LCC(p) / ((1 - p) N) with p = removed / N: the largest
+  // component as a fraction of the nodes left; 0 once none is left
+  auto n1 = [&](uint32_t q) -> double {
+    const uint32_t left = n - removed[q];
+    return left ? (double)lcc[q] / (double)left : 0.0;
+  };
+  const double base = n_runs ? n1(0) : 0.0;
+  for (uint32_t q = 0; q < n_runs; ++q) {
+    const double v = n1(q);
+    if (norm1) norm1[q] = v;
+    // LCC_norm,2(p) = LCC_norm,1(p) / LCC_norm,1(0)
+    if (norm2) norm2[q] = base > 0.0 ? v / base : v;
+  }
+  return TCRNET_OK;
+}
+
 }  // extern "C"

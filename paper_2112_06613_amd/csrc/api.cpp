@@ -5,6 +5,7 @@
 
 #include <algorithm>
 #include <chrono>
+#include <cstdio>
 #include <cstring>
 #include <vector>
 
@@ -24,8 +25,10 @@ struct tcrnet_graph {
 };
 
 namespace {
-
 const char kVersion[] = "tcrnet 0.1.0 (gfx950)";
+}  // namespace
+
+namespace tcr {
 
 int32_t check_k(int32_t k) {
   if (k < 0 || k > TCRNET_MAX_K) return set_error(TCRNET_EINVAL, "k = %d outside [0, %d]", k, TCRNET_MAX_K);
@@ -44,6 +47,10 @@ int32_t check_host_seqs(const tcrnet_seqs* s, const char* what) {
   return TCRNET_OK;
 }
 
+}  // namespace tcr
+
+namespace {
+
 uint64_t default_capacity(const tcrnet_ctx* ctx, uint64_t n) {
   if (ctx->opts.edge_capacity) return ctx->opts.edge_capacity;
   uint64_t c = 4 * n;
@@ -54,7 +61,7 @@ uint64_t default_capacity(const tcrnet_ctx* ctx, uint64_t n) {
 
 namespace tcr {
 
-Sched pick_sched(const tcrnet_ctx* ctx, uint64_t n, int k) {
+Sched pick_sched(const tcrnet_ctx* ctx, uint64_t n, int k, int form) {
   Sched s;
   // Pattern masks in LDS leave the pair kernel 79 VGPRs (six waves per SIMD
   // instead of five): faster once a launch keeps the chip full for most of
@@ -67,8 +74,15 @@ Sched pick_sched(const tcrnet_ctx* ctx, uint64_t n, int k) {
   s.peq_lds = n >= kPeqLdsMinSeqs;
   s.texts_per_item = default_texts_per_item(n);
   if (!(ctx->opts.flags & TCRNET_F_NO_AUTOTUNE)) {
-    auto it = ctx->tuned.find(std::make_pair((int)bits_for(n ? n : 1), k));
-    if (it != ctx->tuned.end()) s = it->second;
+    TuneKey key;
+    key.form = form;
+    key.size_class = (int)bits_for(n ? n : 1);
+    key.k = k;
+    auto it = ctx->tuned.find(key);
+    if (it != ctx->tuned.end()) {
+      s = it->second.sched;
+      s.tuned = true;
+    }
   }
   if (ctx->opts.texts_per_item) s.texts_per_item = ctx->opts.texts_per_item;
   if (ctx->opts.waves_per_simd) s.waves_per_simd = ctx->opts.waves_per_simd;
@@ -93,6 +107,7 @@ int32_t run_pipeline(tcrnet_ctx* ctx, Pipeline& pl, PipeParams pp, hipStream_t s
   inf.waves_per_simd = sched.waves_per_simd;
   inf.peq_lds = sched.peq_lds ? 1 : 0;
   inf.pack = sched.pack ? 1 : 0;
+  inf.tuned = sched.tuned ? 1 : 0;
   if (pp.n == 0) {
     *E = 0;
     if (info) *info = inf;
@@ -156,6 +171,8 @@ int32_t tcrnet_ctx_create(int32_t device, const tcrnet_opts* opts, tcrnet_ctx** 
   if ((e = hipSetDevice(device)) != hipSuccess) return hip_error(e, "hipSetDevice");
   tcrnet_ctx* c = new tcrnet_ctx();
   c->device = device;
+  snprintf(c->arch, sizeof c->arch, "%s", prop.gcnArchName);
+  c->cus = prop.multiProcessorCount;
   if (opts) c->opts = *opts;
   if ((e = hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking)) != hipSuccess) {
     delete c;
@@ -165,7 +182,7 @@ int32_t tcrnet_ctx_create(int32_t device, const tcrnet_opts* opts, tcrnet_ctx** 
   (void)hipEventCreate(&c->ev_p1);
   (void)hipEventCreate(&c->ev_b0);
   (void)hipEventCreate(&c->ev_b1);
-  if ((e = hipHostMalloc((void**)&c->h_meta, sizeof(Meta), hipHostMallocDefault)) != hipSuccess) {
+  if ((e = host_malloc((void**)&c->h_meta, sizeof(Meta))) != hipSuccess) {
     c->h_meta = nullptr;
     (void)tcrnet_ctx_destroy(c);
     return hip_error(e, "pinned host allocation");
@@ -204,6 +221,8 @@ const char* tcrnet_status_string(int32_t s) {
 }
 
 const char* tcrnet_version(void) { return kVersion; }
+
+void tcrnet_debug_fail_alloc(int64_t after) { arm_alloc_failure(after); }
 
 // ----------------------------------------------------------------- builds
 static int32_t build_host(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k, bool weighted, tcrnet_graph** out) {
@@ -344,121 +363,20 @@ int32_t tcrnet_build_batch(tcrnet_ctx* ctx, const tcrnet_seqs* reps, uint32_t n_
   for (uint32_t r = 0; r < n_reps; ++r) outs[r] = nullptr;
   int32_t rc;
   if ((rc = check_k(k))) return rc;
-  for (uint32_t r = 0; r < n_reps; ++r)
-    if ((rc = check_host_seqs(&reps[r], "tcrnet_build_batch"))) return rc;
   (void)hipSetDevice(ctx->device);
-  // concatenate all repertoires; segment r holds global ids [seg[r], seg[r+1])
-  std::vector<uint32_t> seg(n_reps + 1, 0);
-  uint64_t bytes = 0, total = 0;
-  for (uint32_t r = 0; r < n_reps; ++r) {
-    total += reps[r].n;
-    if (total > TCRNET_MAX_SEQS) return set_error(TCRNET_EINVAL, "more than 2^28 sequences in one batch");
-    seg[r + 1] = (uint32_t)total;
-    if (reps[r].n) bytes += reps[r].offsets[reps[r].n] - reps[r].offsets[0];
-  }
-  const uint32_t n = (uint32_t)total;
-  std::vector<uint64_t> off(n + 1);
-  std::vector<char>& hdata = ctx->batch_host;
-  hdata.resize(bytes ? bytes : 1);
-  {
-    uint64_t pos = 0;
-    uint32_t i = 0;
-    for (uint32_t r = 0; r < n_reps; ++r) {
-      const tcrnet_seqs& s = reps[r];
-      if (!s.n) continue;
-      const uint64_t b0 = s.offsets[0], nb = s.offsets[s.n] - b0;
-      memcpy(hdata.data() + pos, s.data + b0, nb);
-      for (uint32_t q = 0; q < s.n; ++q) off[i++] = pos + (s.offsets[q] - b0);
-      pos += nb;
-    }
-    off[n] = pos;
-  }
-  hipError_t e;
-  if ((e = ctx->in_data.ensure(bytes ? bytes : 1)) != hipSuccess) return hip_error(e, "input allocation");
-  if ((e = ctx->in_off.ensure((uint64_t)(n + 1) * 8)) != hipSuccess) return hip_error(e, "input allocation");
-  if ((e = ctx->in_seg.ensure((uint64_t)(n_reps + 1) * 4)) != hipSuccess) return hip_error(e, "input allocation");
-  if ((e = ctx->out_deg.ensure((uint64_t)(n ? n : 1) * 4)) != hipSuccess) return hip_error(e, "output allocation");
-  if (bytes) (void)hipMemcpyAsync(ctx->in_data.p, hdata.data(), bytes, hipMemcpyHostToDevice, ctx->stream);
-  (void)hipMemcpyAsync(ctx->in_off.p, off.data(), (uint64_t)(n + 1) * 8, hipMemcpyHostToDevice, ctx->stream);
-  (void)hipMemcpyAsync(ctx->in_seg.p, seg.data(), (uint64_t)(n_reps + 1) * 4, hipMemcpyHostToDevice, ctx->stream);
-
-  PipeParams pp;
-  pp.d_data = ctx->in_data.as<char>();
-  pp.d_off = ctx->in_off.as<uint64_t>();
-  pp.n = n;
-  pp.d_segoff = ctx->in_seg.as<uint32_t>();
-  pp.n_seg = n_reps ? n_reps : 1;
-  pp.k = k;
-  pp.capacity = default_capacity(ctx, n);
-  pp.d_deg = ctx->out_deg.as<int32_t>();
-  // one launch over all repertoires: its work items are sized for the whole
-  // launch (256 repertoires of 1,000-40,000 sequences, 2.75 M in all: 21.1 ms
-  // at 8,192 texts per item, 21.9 ms at 512)
-  Sched sched = pick_sched(ctx, n, k);
-  pp.sched = sched;
+  BatchInput bi;
+  if ((rc = batch_upload(ctx, reps, n_reps, &bi))) return rc;
+  const Sched sched = pick_sched(ctx, bi.n, k, kFormBatch);
   tcrnet_build_info info{};
-  info.texts_per_item = sched.texts_per_item;
-  info.waves_per_simd = sched.waves_per_simd;
-  info.peq_lds = sched.peq_lds;
-  info.pack = sched.pack;
   uint64_t E = 0;
-  if (n > 0) {
-    for (int attempt = 0; attempt < 2; ++attempt) {
-      if ((e = pipeline_reserve(ctx->pipe, n, pp.n_seg, k, sched.texts_per_item, pp.capacity)) != hipSuccess)
-        return hip_error(e, "workspace allocation");
-      if ((e = ctx->out_pairs.ensure(pp.capacity * 8)) != hipSuccess) return hip_error(e, "output allocation");
-      pp.d_pairs = ctx->out_pairs.as<uint32_t>();
-      // one HIP graph for the whole launch sequence, re-captured only when
-      // the shape or a buffer changes
-      BatchKey key{n, pp.n_seg, k, sched.texts_per_item, sched.waves_per_simd, sched.peq_lds, sched.pack,
-                   pp.capacity,
-                   ctx->pipe.rec.p, ctx->pipe.edges.p, ctx->pipe.tmp.p, ctx->out_pairs.p, ctx->in_data.p};
-      if (!ctx->batch_exec || !(key == ctx->batch_key)) {
-        if (ctx->batch_exec) {
-          (void)hipGraphExecDestroy(ctx->batch_exec);
-          ctx->batch_exec = nullptr;
-        }
-        hipGraph_t graph = nullptr;
-        if ((e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
-          return hip_error(e, "graph capture");
-        pipeline_enqueue(ctx->pipe, pp, ctx->device, ctx->stream, nullptr, nullptr);
-        if ((e = hipStreamEndCapture(ctx->stream, &graph)) != hipSuccess) return hip_error(e, "graph capture");
-        e = hipGraphInstantiate(&ctx->batch_exec, graph, nullptr, nullptr, 0);
-        (void)hipGraphDestroy(graph);
-        if (e != hipSuccess) {
-          ctx->batch_exec = nullptr;
-          return hip_error(e, "graph instantiate");
-        }
-        ctx->batch_key = key;
-      }
-      (void)hipEventRecord(ctx->ev_b0, ctx->stream);
-      if ((e = hipGraphLaunch(ctx->batch_exec, ctx->stream)) != hipSuccess) return hip_error(e, "graph launch");
-      (void)hipEventRecord(ctx->ev_b1, ctx->stream);
-      if ((e = pipeline_meta(ctx->pipe, ctx->h_meta, ctx->stream)) != hipSuccess) return hip_error(e, "batch build");
-      const Meta m = *ctx->h_meta;
-      float bt = 0.f;
-      (void)hipEventElapsedTime(&bt, ctx->ev_b0, ctx->ev_b1);
-      info.build_ms += bt;
-      info.pair_launches += 1;
-      info.evaluated_pairs = m.plan.evaluated_pairs;
-      if (m.cnt.fault) return set_error(TCRNET_EDEVICE, "device sort stalled (internal)");
-      if (m.cnt.err != kNoError) {
-        const unsigned long long idx = m.cnt.err >> 2;
-        const uint32_t r = (uint32_t)(std::upper_bound(seg.begin(), seg.end(), (uint32_t)idx) - seg.begin()) - 1;
-        return set_error(TCRNET_EINVAL, "repertoire %u, %s", r,
-                         input_error_message(((idx - seg[r]) << 2) | (m.cnt.err & 3u)).c_str());
-      }
-      if (m.plan.pad) return set_error(TCRNET_EDEVICE, "work plan overflow (internal)");
-      E = m.cnt.edges;
-      if (E <= pp.capacity) break;
-      pp.capacity = E + E / 16 + 1024;
-      if (attempt == 1) return set_error(TCRNET_EDEVICE, "edge count changed between runs (internal)");
-    }
-  }
+  if ((rc = batch_launch(ctx, bi, k, sched, &E, &info))) return rc;
   // split by repertoire: edges are sorted by global (i, j), so each
   // repertoire's edges are one contiguous run
+  const uint32_t n = bi.n;
+  const std::vector<uint32_t>& seg = bi.seg;
   std::vector<uint32_t> all(2 * E);
   std::vector<int32_t> deg(n);
+  hipError_t e;
   if (E) (void)hipMemcpyAsync(all.data(), ctx->out_pairs.p, E * 8, hipMemcpyDeviceToHost, ctx->stream);
   if (n) (void)hipMemcpyAsync(deg.data(), ctx->out_deg.p, (uint64_t)n * 4, hipMemcpyDeviceToHost, ctx->stream);
   if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return hip_error(e, "result copy");
@@ -485,64 +403,160 @@ int32_t tcrnet_build_batch(tcrnet_ctx* ctx, const tcrnet_seqs* reps, uint32_t n_
   return TCRNET_OK;
 }
 
-// --------------------------------------------------------------- autotune
-int32_t tcrnet_autotune(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k) {
-  if (!ctx) return set_error(TCRNET_EINVAL, "NULL context");
+}  // extern "C"
+
+namespace tcr {
+
+// Concatenate the repertoires (segment r holds global ids [seg[r], seg[r+1]))
+// and copy them to the context's input buffers.
+int32_t batch_upload(tcrnet_ctx* ctx, const tcrnet_seqs* reps, uint32_t n_reps, BatchInput* bi) {
   int32_t rc;
-  if ((rc = check_k(k)) || (rc = check_host_seqs(seqs, "tcrnet_autotune"))) return rc;
-  if (seqs->n < 2) return TCRNET_OK;
-  (void)hipSetDevice(ctx->device);
-  const uint32_t n = seqs->n;
-  const uint64_t base = seqs->offsets[0];
-  const uint64_t bytes = seqs->offsets[n] - base;
+  for (uint32_t r = 0; r < n_reps; ++r)
+    if ((rc = check_host_seqs(&reps[r], "tcrnet_build_batch"))) return rc;
+  std::vector<uint32_t>& seg = bi->seg;
+  seg.assign(n_reps + 1, 0);
+  uint64_t bytes = 0, total = 0;
+  for (uint32_t r = 0; r < n_reps; ++r) {
+    total += reps[r].n;
+    if (total > TCRNET_MAX_SEQS) return set_error(TCRNET_EINVAL, "more than 2^28 sequences in one batch");
+    seg[r + 1] = (uint32_t)total;
+    if (reps[r].n) bytes += reps[r].offsets[reps[r].n] - reps[r].offsets[0];
+  }
+  const uint32_t n = (uint32_t)total;
+  bi->n = n;
+  bi->n_reps = n_reps;
   std::vector<uint64_t> off(n + 1);
-  for (uint32_t i = 0; i <= n; ++i) off[i] = seqs->offsets[i] - base;
+  std::vector<char>& hdata = ctx->batch_host;
+  hdata.resize(bytes ? bytes : 1);
+  {
+    uint64_t pos = 0;
+    uint32_t i = 0;
+    for (uint32_t r = 0; r < n_reps; ++r) {
+      const tcrnet_seqs& s = reps[r];
+      if (!s.n) continue;
+      const uint64_t b0 = s.offsets[0], nb = s.offsets[s.n] - b0;
+      memcpy(hdata.data() + pos, s.data + b0, nb);
+      for (uint32_t q = 0; q < s.n; ++q) off[i++] = pos + (s.offsets[q] - b0);
+      pos += nb;
+    }
+    off[n] = pos;
+  }
   hipError_t e;
   if ((e = ctx->in_data.ensure(bytes ? bytes : 1)) != hipSuccess) return hip_error(e, "input allocation");
-  if ((e = ctx->in_off.ensure((n + 1) * 8)) != hipSuccess) return hip_error(e, "input allocation");
-  if ((e = ctx->out_deg.ensure((uint64_t)n * 4)) != hipSuccess) return hip_error(e, "output allocation");
-  (void)hipMemcpyAsync(ctx->in_data.p, seqs->data + base, bytes, hipMemcpyHostToDevice, ctx->stream);
-  (void)hipMemcpyAsync(ctx->in_off.p, off.data(), (n + 1) * 8, hipMemcpyHostToDevice, ctx->stream);
-  const uint32_t saved_flags = ctx->opts.flags;
-  const tcrnet_opts saved = ctx->opts;
-  const uint32_t Ts[] = {1024, 4096, 16384, 65536};
-  const uint32_t Ws[] = {4, 8};
-  const bool Ls[] = {false, true};
-  double best = 1e30;
-  Sched best_s;
-  for (uint32_t T : Ts)
-    for (uint32_t W : Ws)
-      for (bool L : Ls) {
-        ctx->opts = saved;
-        ctx->opts.flags = (saved_flags | TCRNET_F_NO_AUTOTUNE) & ~(TCRNET_F_PEQ_LDS | TCRNET_F_PEQ_VGPR);
-        ctx->opts.flags |= L ? TCRNET_F_PEQ_LDS : TCRNET_F_PEQ_VGPR;
-        ctx->opts.texts_per_item = T;
-        ctx->opts.waves_per_simd = W;
-        PipeParams pp;
-        pp.d_data = ctx->in_data.as<char>();
-        pp.d_off = ctx->in_off.as<uint64_t>();
-        pp.n = n;
-        pp.k = k;
-        pp.capacity = default_capacity(ctx, n);
-        pp.d_deg = ctx->out_deg.as<int32_t>();
-        uint64_t E = 0;
-        tcrnet_build_info info{};
-        rc = run_pipeline(ctx, ctx->pipe, pp, ctx->stream, true, &ctx->out_pairs, &E, &info);
-        if (rc) {
-          ctx->opts = saved;
-          return rc;
-        }
-        const double t = info.pair_kernel_ms / (info.pair_launches ? info.pair_launches : 1);
-        if (t < best) {
-          best = t;
-          best_s.texts_per_item = T;
-          best_s.waves_per_simd = W;
-          best_s.peq_lds = L;
-        }
-      }
-  ctx->opts = saved;
-  ctx->tuned[std::make_pair((int)bits_for(n), (int)k)] = best_s;
+  if ((e = ctx->in_off.ensure((uint64_t)(n + 1) * 8)) != hipSuccess) return hip_error(e, "input allocation");
+  if ((e = ctx->in_seg.ensure((uint64_t)(n_reps + 1) * 4)) != hipSuccess) return hip_error(e, "input allocation");
+  if ((e = ctx->out_deg.ensure((uint64_t)(n ? n : 1) * 4)) != hipSuccess) return hip_error(e, "output allocation");
+  if (bytes && (e = hipMemcpyAsync(ctx->in_data.p, hdata.data(), bytes, hipMemcpyHostToDevice, ctx->stream)) !=
+                   hipSuccess)
+    return hip_error(e, "input copy");
+  if ((e = hipMemcpyAsync(ctx->in_off.p, off.data(), (uint64_t)(n + 1) * 8, hipMemcpyHostToDevice, ctx->stream)) !=
+      hipSuccess)
+    return hip_error(e, "input copy");
+  if ((e = hipMemcpyAsync(ctx->in_seg.p, seg.data(), (uint64_t)(n_reps + 1) * 4, hipMemcpyHostToDevice,
+                          ctx->stream)) != hipSuccess)
+    return hip_error(e, "input copy");
+  // the host vectors are read by the copies above: wait before they go
+  if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return hip_error(e, "input copy");
   return TCRNET_OK;
 }
 
-}  // extern "C"
+// One batched launch of the uploaded input: the whole launch sequence
+// (counters, encode, sort, plan, pairs, canonicalise) as one HIP graph,
+// captured again only when the shape or a buffer changed, then replayed.
+// Re-runs once with the exact edge capacity after an overflow.
+int32_t batch_launch(tcrnet_ctx* ctx, const BatchInput& bi, int32_t k, const Sched& sched, uint64_t* E_out,
+                     tcrnet_build_info* info_out) {
+  const uint32_t n = bi.n;
+  PipeParams pp;
+  pp.d_data = ctx->in_data.as<char>();
+  pp.d_off = ctx->in_off.as<uint64_t>();
+  pp.n = n;
+  pp.d_segoff = ctx->in_seg.as<uint32_t>();
+  pp.n_seg = bi.n_reps ? bi.n_reps : 1;
+  pp.k = k;
+  pp.capacity = ctx->opts.edge_capacity ? ctx->opts.edge_capacity : std::max<uint64_t>(65536, 4ull * n);
+  pp.d_deg = ctx->out_deg.as<int32_t>();
+  pp.sched = sched;
+  tcrnet_build_info info{};
+  info.texts_per_item = sched.texts_per_item;
+  info.waves_per_simd = sched.waves_per_simd;
+  info.peq_lds = sched.peq_lds;
+  info.pack = sched.pack;
+  info.tuned = sched.tuned;
+  uint64_t E = 0;
+  hipError_t e;
+  if (n > 0) {
+    for (int attempt = 0; attempt < 2; ++attempt) {
+      if ((e = pipeline_reserve(ctx->pipe, n, pp.n_seg, k, sched.texts_per_item, pp.capacity)) != hipSuccess)
+        return hip_error(e, "workspace allocation");
+      if ((e = ctx->out_pairs.ensure(pp.capacity * 8)) != hipSuccess) return hip_error(e, "output allocation");
+      pp.d_pairs = ctx->out_pairs.as<uint32_t>();
+      BatchKey key;
+      key.n = n;
+      key.n_seg = pp.n_seg;
+      key.k = k;
+      key.T = sched.texts_per_item;
+      key.W = sched.waves_per_simd;
+      key.lds = sched.peq_lds;
+      key.pack = sched.pack;
+      key.capacity = pp.capacity;
+      key.desc_cap = ctx->pipe.desc_cap;
+      {
+        Pipeline& pl = ctx->pipe;
+        const DevBuf* used[] = {&pl.rec,   &pl.key,   &pl.key2,   &pl.val,     &pl.val2,       &pl.srec,
+                                &pl.speq,  &pl.off,   &pl.descs,  &pl.ibase,   &pl.meta,       &pl.tmp,
+                                &pl.edges, &pl.edist, &pl.ekeys,  &pl.ekeys2,  &ctx->in_data,  &ctx->in_off,
+                                &ctx->in_seg, &ctx->out_pairs, &ctx->out_deg};
+        for (const DevBuf* b : used) key.bufs.emplace_back(b->p, b->cap);
+      }
+      if (!ctx->batch_exec || !(key == ctx->batch_key)) {
+        if (ctx->batch_exec) {
+          (void)hipGraphExecDestroy(ctx->batch_exec);
+          ctx->batch_exec = nullptr;
+        }
+        hipGraph_t graph = nullptr;
+        if ((e = hipStreamBeginCapture(ctx->stream, hipStreamCaptureModeThreadLocal)) != hipSuccess)
+          return hip_error(e, "graph capture");
+        pipeline_enqueue(ctx->pipe, pp, ctx->device, ctx->stream, nullptr, nullptr);
+        if ((e = hipStreamEndCapture(ctx->stream, &graph)) != hipSuccess) return hip_error(e, "graph capture");
+        e = hipGraphInstantiate(&ctx->batch_exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) {
+          ctx->batch_exec = nullptr;
+          return hip_error(e, "graph instantiate");
+        }
+        ctx->batch_key = key;
+        ctx->batch_captures++;
+        info.graph_captured = 1;
+      }
+      (void)hipEventRecord(ctx->ev_b0, ctx->stream);
+      if ((e = hipGraphLaunch(ctx->batch_exec, ctx->stream)) != hipSuccess) return hip_error(e, "graph launch");
+      (void)hipEventRecord(ctx->ev_b1, ctx->stream);
+      if ((e = pipeline_meta(ctx->pipe, ctx->h_meta, ctx->stream)) != hipSuccess) return hip_error(e, "batch build");
+      const Meta m = *ctx->h_meta;
+      float bt = 0.f;
+      (void)hipEventElapsedTime(&bt, ctx->ev_b0, ctx->ev_b1);
+      info.build_ms += bt;
+      info.pair_launches += 1;
+      info.evaluated_pairs = m.plan.evaluated_pairs;
+      if (m.cnt.fault) return set_error(TCRNET_EDEVICE, "device sort stalled (internal)");
+      if (m.cnt.err != kNoError) {
+        const std::vector<uint32_t>& seg = bi.seg;
+        const unsigned long long idx = m.cnt.err >> 2;
+        const uint32_t r = (uint32_t)(std::upper_bound(seg.begin(), seg.end(), (uint32_t)idx) - seg.begin()) - 1;
+        return set_error(TCRNET_EINVAL, "repertoire %u, %s", r,
+                         input_error_message(((idx - seg[r]) << 2) | (m.cnt.err & 3u)).c_str());
+      }
+      if (m.plan.pad) return set_error(TCRNET_EDEVICE, "work plan overflow (internal)");
+      E = m.cnt.edges;
+      if (E <= pp.capacity) break;
+      pp.capacity = E + E / 16 + 1024;
+      if (attempt == 1) return set_error(TCRNET_EDEVICE, "edge count changed between runs (internal)");
+    }
+  }
+  *E_out = E;
+  *info_out = info;
+  return TCRNET_OK;
+}
+
+}  // namespace tcr

@@ -3,13 +3,41 @@
 // captured in a HIP graph).
 #include "pipeline.h"
 
+#include <atomic>
 #include <cstdio>
 
 namespace tcr {
 
 namespace {
 thread_local std::string g_last_error;
+std::atomic<int64_t> g_fail_after{-1};  // successful allocations before an injected failure (-1: none)
+
+bool injected_failure() {
+  int64_t v = g_fail_after.load();
+  while (v >= 0) {
+    if (g_fail_after.compare_exchange_weak(v, v - 1)) return v == 0;
+  }
+  return false;
 }
+}  // namespace
+
+hipError_t dev_malloc(void** p, size_t bytes) {
+  if (injected_failure()) {
+    *p = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  return hipMalloc(p, bytes);
+}
+
+hipError_t host_malloc(void** p, size_t bytes) {
+  if (injected_failure()) {
+    *p = nullptr;
+    return hipErrorOutOfMemory;
+  }
+  return hipHostMalloc(p, bytes, hipHostMallocDefault);
+}
+
+void arm_alloc_failure(int64_t after) { g_fail_after.store(after < 0 ? -1 : after); }
 
 const char* last_error_text() { return g_last_error.c_str(); }
 void clear_error() { g_last_error.clear(); }

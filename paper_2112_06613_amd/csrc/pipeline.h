@@ -8,6 +8,13 @@
 
 namespace tcr {
 
+// Device and pinned-host allocation with an optional injected failure
+// (tcrnet_debug_fail_alloc): the allocation after the armed number of
+// successful ones reports hipErrorOutOfMemory, once.
+hipError_t dev_malloc(void** p, size_t bytes);
+hipError_t host_malloc(void** p, size_t bytes);
+void arm_alloc_failure(int64_t after);  // -1: disarm
+
 // Grow-only device buffer.
 struct DevBuf {
   void* p = nullptr;
@@ -25,7 +32,7 @@ struct DevBuf {
     if (bytes <= cap && p) return hipSuccess;
     release();
     const size_t nb = bytes < 256 ? 256 : bytes + bytes / 8;
-    hipError_t e = hipMalloc(&p, nb);
+    hipError_t e = dev_malloc(&p, nb);
     if (e == hipSuccess) cap = nb;
     else p = nullptr;
     return e;
@@ -53,6 +60,7 @@ struct Sched {
   uint32_t waves_per_simd = 8;
   bool peq_lds = false;
   bool pack = true;  // two patterns per lane for patterns of <= 16 residues
+  bool tuned = false;  // chosen by the autotuner
 };
 
 // Device buffers of one build pipeline (encode -> sort -> bucket -> plan ->

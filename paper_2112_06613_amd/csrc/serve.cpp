@@ -85,6 +85,7 @@ struct Request {
   std::vector<SegPtr> snap;
   uint32_t n_snap = 0;
   SegPtr new_seg;
+  bool published = false;  // insert: its segment is part of the repertoire
   uint64_t bytes = 0;
   // outcome
   bool done = false;
@@ -108,7 +109,7 @@ struct Pinned {
     if (bytes <= cap && p) return hipSuccess;
     release();
     size_t nb = bytes < 4096 ? 4096 : bytes + bytes / 4;
-    hipError_t e = hipHostMalloc(&p, nb, hipHostMallocDefault);
+    hipError_t e = host_malloc(&p, nb);
     if (e == hipSuccess) cap = nb;
     else p = nullptr;
     return e;
@@ -158,17 +159,18 @@ struct tcrnet_index {
   std::unordered_map<uint64_t, Request*> reqs;
   uint64_t next_ticket = 1, next_seqno = 1;
   bool stop = false;
+  // An insert whose segment was published but whose edges or degrees were
+  // not (a failure after admission), or a failed merge, leaves the resident
+  // network inconsistent: the index then fails every request admitted after
+  // that point and every later call (TCRNET_ESTATE).
+  uint64_t failed_seqno = 0;  // 0: healthy
+  std::string failed_msg;
   uint32_t inflight = 0;
   std::thread worker;
   std::vector<int32_t> host_deg;
 };
 
 namespace {
-
-int32_t check_k(int32_t k) {
-  if (k < 0 || k > TCRNET_MAX_K) return set_error(TCRNET_EINVAL, "k = %d outside [0, %d]", k, TCRNET_MAX_K);
-  return TCRNET_OK;
-}
 
 // Residue and length checks of host input (argument validation before a
 // request can change the repertoire; the kernels check again).
@@ -228,10 +230,32 @@ void finish(tcrnet_index* idx, Slot* s, Request* r) {
   idx->cv_done.notify_all();
 }
 
+int32_t status_of(hipError_t e) { return e == hipErrorOutOfMemory ? TCRNET_ENOMEM : TCRNET_EDEVICE; }
+
+// Mark the index failed from admission `seqno` on (under mu).
+void mark_failed_locked(tcrnet_index* idx, uint64_t seqno, const std::string& why) {
+  if (idx->failed_seqno == 0 || seqno < idx->failed_seqno) {
+    idx->failed_seqno = seqno ? seqno : 1;
+    idx->failed_msg = why;
+  }
+}
+
 void fail_request(tcrnet_index* idx, Slot* s, Request* r, int32_t status, const std::string& msg) {
+  if (r->insert && r->published) {
+    std::lock_guard<std::mutex> g(idx->mu);
+    mark_failed_locked(idx, r->seqno, "insert (admission " + std::to_string(r->seqno) + ") failed: " + msg);
+  }
   r->status = status;
   r->err = msg;
   finish(idx, s, r);
+}
+
+// A request admitted after the index failed sees an inconsistent repertoire.
+bool after_failure(tcrnet_index* idx, const Request* r, std::string* why) {
+  std::lock_guard<std::mutex> g(idx->mu);
+  if (idx->failed_seqno == 0 || r->seqno < idx->failed_seqno) return false;
+  *why = "index failed: " + idx->failed_msg;
+  return true;
 }
 
 // Stage 2+3 of a request on its slot: plan the parts, pair kernel, canonical
@@ -315,6 +339,7 @@ hipError_t admit(tcrnet_index* idx, Slot* s, Request* r) {
       qref = r->new_seg->ref();
       idx->segs.push_back(r->new_seg);
       idx->n_total += r->m;
+      r->published = true;
     } else {
       qref.srec = s->pl.srec.as<SeqRec>();
       qref.speq = s->pl.speq.as<PeqRec>();
@@ -386,6 +411,11 @@ hipError_t merge_segments(tcrnet_index* idx) {
 // Checkpoint 1: counters are on the host.
 void on_meta(tcrnet_index* idx, Slot* s) {
   Request* r = s->req;
+  std::string why;
+  if (after_failure(idx, r, &why)) {
+    fail_request(idx, s, r, TCRNET_ESTATE, why);
+    return;
+  }
   const Meta m = *s->h_meta.as<Meta>();
   if (m.cnt.fault) {
     fail_request(idx, s, r, TCRNET_EDEVICE, "device sort stalled (internal)");
@@ -413,7 +443,7 @@ void on_meta(tcrnet_index* idx, Slot* s) {
       r->bytes = request_bytes(r->m, s->capacity, s->n_parts);
       idx->used += r->bytes;
     }
-    if ((e = enqueue_pairs(idx, s)) != hipSuccess) fail_request(idx, s, r, TCRNET_EDEVICE, hipGetErrorString(e));
+    if ((e = enqueue_pairs(idx, s)) != hipSuccess) fail_request(idx, s, r, status_of(e), hipGetErrorString(e));
     return;
   }
   if (r->insert)
@@ -436,6 +466,13 @@ void on_meta(tcrnet_index* idx, Slot* s) {
 void on_done(tcrnet_index* idx, Slot* s) {
   Request* r = s->req;
   tcrnet_result* res = r->res;
+  std::string why;
+  if (after_failure(idx, r, &why)) {
+    delete res;
+    r->res = nullptr;
+    fail_request(idx, s, r, TCRNET_ESTATE, why);
+    return;
+  }
   if (!res->pairs.empty()) memcpy(res->pairs.data(), s->h_pairs.p, res->pairs.size() * 4);
   res->counts.assign(s->h_counts.as<int32_t>(), s->h_counts.as<int32_t>() + r->m);
   float dev_ms = 0.f;
@@ -466,6 +503,14 @@ void worker_loop(tcrnet_index* idx) {
           }
         if (!free_slot) break;
         r = idx->pending.front();
+        if (idx->failed_seqno) {
+          idx->pending.pop_front();
+          const std::string why = "index failed: " + idx->failed_msg;
+          lk.unlock();
+          fail_request(idx, nullptr, r, TCRNET_ESTATE, why);
+          progressed = true;
+          continue;
+        }
         const uint32_t n_parts = (uint32_t)idx->segs.size() + 1;
         const uint64_t need = request_bytes(r->m, std::max<uint64_t>(4096, (uint64_t)r->m * 16), n_parts);
         if (need > idx->budget) {
@@ -489,11 +534,12 @@ void worker_loop(tcrnet_index* idx) {
         idx->inflight++;
       }
       hipError_t e = admit(idx, free_slot, r);
-      if (e != hipSuccess) fail_request(idx, free_slot, r, TCRNET_EDEVICE, hipGetErrorString(e));
+      if (e != hipSuccess) fail_request(idx, free_slot, r, status_of(e), hipGetErrorString(e));
       if (idx->segs.size() > 1 + kMaxDeltas) {
         if ((e = merge_segments(idx)) != hipSuccess) {
           std::lock_guard<std::mutex> g(idx->mu);
-          idx->stop = true;  // the repertoire can no longer be served correctly
+          // later admissions would see a partly merged repertoire
+          mark_failed_locked(idx, idx->next_seqno, std::string("segment merge failed: ") + hipGetErrorString(e));
         }
       }
       progressed = true;
@@ -635,12 +681,9 @@ int32_t tcrnet_index_create(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k_
 int32_t tcrnet_index_size(tcrnet_index* idx, uint32_t* n) {
   if (!idx || !n) return set_error(TCRNET_EINVAL, "NULL argument");
   std::lock_guard<std::mutex> g(idx->mu);
-  uint32_t pend = 0;
-  for (Request* r : idx->pending)
-    if (r->insert) pend += r->m;
+  if (idx->failed_seqno) return set_error(TCRNET_ESTATE, "index failed: %s", idx->failed_msg.c_str());
   // admitted inserts are counted in n_total; queued ones are not yet part of it
   *n = idx->n_total;
-  (void)pend;
   return TCRNET_OK;
 }
 
@@ -649,6 +692,7 @@ int32_t tcrnet_index_degree(tcrnet_index* idx, const int32_t** degree, uint32_t*
   {
     std::unique_lock<std::mutex> lk(idx->mu);
     idx->cv_done.wait(lk, [&] { return idx->pending.empty() && idx->inflight == 0; });
+    if (idx->failed_seqno) return set_error(TCRNET_ESTATE, "index failed: %s", idx->failed_msg.c_str());
   }
   (void)hipSetDevice(idx->device);
   const uint32_t total = idx->n_total;
@@ -701,6 +745,10 @@ int32_t tcrnet_submit(tcrnet_index* idx, const tcrnet_seqs* q, int32_t k, int32_
   if (idx->stop) {
     delete r;
     return set_error(TCRNET_ESTATE, "index is shutting down");
+  }
+  if (idx->failed_seqno) {
+    delete r;
+    return set_error(TCRNET_ESTATE, "index failed: %s", idx->failed_msg.c_str());
   }
   if (r->insert) {
     // every accepted insert will be resident: keep the total in range

@@ -58,6 +58,15 @@ def test_medium_k1_against_closed_form(tn, ctx, orc):
     _eq(g, e, d)
 
 
+def test_medium_k2_full_oracle(tn, ctx, orc):
+    # N = 50,000 at k = 2: the whole edge list and degree array against the
+    # full-table DP over all 1.25e9 pairs (about 30 s on 16 host threads)
+    s = synth.medium()
+    g = tn.tcrnet_build(ctx, s, 2)
+    e, d = orc.build(s, 2)
+    _eq(g, e, d)
+
+
 def test_medium_k2_sampled_rows_and_soundness(tn, ctx, orc):
     s = synth.medium()
     g = tn.tcrnet_build(ctx, s, 2)
@@ -283,3 +292,29 @@ def test_valu_peak_probe(tn, ctx):
     rate, sec = tn.tcrnet_valu_peak(ctx)
     assert sec > 0
     assert 0.5 * 256 * 64 * 2.4e9 < rate < 1.05 * 256 * 128 * 2.4e9
+
+
+def test_injected_allocation_failures_are_clean(tn, orc):
+    """Every device or pinned allocation of a build failing in turn: the call
+    returns TCRNET_ENOMEM with no result, and the next call on the same
+    context is correct."""
+    s = synth.repertoire(3000, 300, 77)
+    e, d = orc.build(s, 1)
+    lib = tn.load_library()
+    failures = 0
+    try:
+        for after in range(40):
+            with tn.Context(0) as c:
+                lib.tcrnet_debug_fail_alloc(after)
+                try:
+                    g = tn.tcrnet_build(c, s, 1)
+                except tn.TcrnetError as err:
+                    assert err.status == tn.TCRNET_ENOMEM, err
+                    failures += 1
+                    lib.tcrnet_debug_fail_alloc(-1)
+                    g = tn.tcrnet_build(c, s, 1)
+                lib.tcrnet_debug_fail_alloc(-1)
+                _eq(g, e, d)
+    finally:
+        lib.tcrnet_debug_fail_alloc(-1)
+    assert failures >= 10   # the sweep reached the build's allocations

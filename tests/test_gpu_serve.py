@@ -177,3 +177,115 @@ def test_request_errors(tn, ctx):
         # still serving
         r = tn.tcrnet_query(idx, base.subset([3]), 0)
         assert (0, 3) in set(map(tuple, r.pairs.tolist()))
+
+
+def _insert_ref_cross(orc, snap, new, k):
+    """Insert reference without the O(N^2) rebuild: the new sequences against
+    the snapshot (oracle query) plus the new sequences among themselves."""
+    n_old = snap.n
+    e1, c1 = orc.query(snap, new, k)          # (q, r) pairs
+    e2, d2 = orc.build(new, k)                # (a, b), a < b
+    parts = []
+    if len(e1):
+        parts.append(np.stack([e1[:, 1], e1[:, 0] + n_old], axis=1).astype(np.uint32))
+    if len(e2):
+        parts.append((e2 + n_old).astype(np.uint32))
+    sel = np.concatenate(parts) if parts else np.zeros((0, 2), dtype=np.uint32)
+    sel = sel[np.lexsort((sel[:, 1], sel[:, 0]))]
+    return sel, (c1 + d2).astype(np.int32)
+
+
+def test_paper_scale_resident_mixed_trace(tn, ctx, orc):
+    """The served form at its real resident size: 800,000 sequences indexed at
+    k = 1, then 26 requests submitted at once -- queries of 1-64 sequences at
+    k in {1, 2} and 10 inserts (so a segment merge of the 800,000-sequence
+    base runs in between).  Every result equals the oracle's answer for its
+    snapshot; the final degrees equal those of the final repertoire."""
+    base = synth.paper_scale()
+    rng = np.random.default_rng(31)
+    reqs = []
+    n_ins = 0
+    for i in range(26):
+        ins = (i % 5 in (1, 3)) or (i > 20 and n_ins < 10)
+        n_ins += ins
+        size = int(np.exp(rng.uniform(0, np.log(64)))) if not ins else int(rng.integers(1, 33))
+        k = 1 if ins else int(rng.integers(1, 3))
+        reqs.append((synth.queries(size, 80000, synth.SEED_PAPER, 5000 + i), k, ins))
+    assert sum(r[2] for r in reqs) >= 9     # more than 8 insert segments: a merge runs
+    with tn.tcrnet_index_create(ctx, base, 1) as idx:
+        tickets = [tn.tcrnet_submit(idx, q, k, ins) for q, k, ins in reqs]
+        results = [tn.tcrnet_wait(idx, t) for t in tickets]
+        final_deg = idx.degree()
+        final_n = idx.size()
+    order = np.argsort([r.info["seqno"] for r in results])
+    snap = base
+    new_edges = []
+    for i in order:
+        q, k, ins = reqs[i]
+        res = results[i]
+        assert res.info["snapshot_size"] == snap.n
+        if ins:
+            sel, cnt = _insert_ref_cross(orc, snap, q, 1)
+            assert np.array_equal(res.pairs, sel), f"insert {i}"
+            assert np.array_equal(res.counts, cnt), f"insert {i}"
+            new_edges.append(sel)
+            snap = snap.concat(q)
+        else:
+            e, c = orc.query(snap, q, k)
+            assert np.array_equal(res.pairs, e), f"query {i}"
+            assert np.array_equal(res.counts, c), f"query {i}"
+    assert final_n == snap.n
+    # final degrees: the base network (k = 1 witness) plus every insert's edges
+    _, d0 = orc.k1_build(base)
+    deg = np.zeros(snap.n, dtype=np.int64)
+    deg[:base.n] = d0
+    for sel in new_edges:
+        np.add.at(deg, sel[:, 0].astype(np.int64), 1)
+        np.add.at(deg, sel[:, 1].astype(np.int64), 1)
+    assert np.array_equal(final_deg, deg.astype(np.int32))
+
+
+def test_insert_failing_after_admission_never_leaves_a_torn_index(tn, orc):
+    """Every allocation of an insert failing in turn: the insert reports
+    TCRNET_ENOMEM and the index is either unchanged (the failure came before
+    the insert's sequences joined the repertoire; later requests are exact)
+    or failed (every later call reports TCRNET_ESTATE) -- never a repertoire
+    with sequences whose edges and degrees are missing."""
+    base = synth.repertoire(2000, 200, 61)
+    new = synth.queries(300, 200, 61, 62)
+    _, d_base = orc.build(base, 1)
+    sel, cnt, d_union = _insert_ref(orc, base, new, 1)
+    lib = tn.load_library()
+    seen_failed = seen_unchanged = 0
+    try:
+        with tn.Context(0) as c:
+            for after in range(30):
+                with tn.tcrnet_index_create(c, base, 1) as idx:
+                    lib.tcrnet_debug_fail_alloc(after)
+                    try:
+                        r = tn.tcrnet_insert(idx, new)
+                        lib.tcrnet_debug_fail_alloc(-1)
+                        assert np.array_equal(r.pairs, sel) and np.array_equal(r.counts, cnt)
+                        assert np.array_equal(idx.degree(), d_union)
+                        continue
+                    except tn.TcrnetError as err:
+                        lib.tcrnet_debug_fail_alloc(-1)
+                        assert err.status == tn.TCRNET_ENOMEM, err
+                    try:
+                        n_now = idx.size()
+                    except tn.TcrnetError as err:
+                        assert err.status == tn.TCRNET_ESTATE
+                        with pytest.raises(tn.TcrnetError) as ei:
+                            tn.tcrnet_query(idx, new, 1)
+                        assert ei.value.status == tn.TCRNET_ESTATE
+                        seen_failed += 1
+                        continue
+                    assert n_now == base.n
+                    assert np.array_equal(idx.degree(), d_base)
+                    r = tn.tcrnet_insert(idx, new)
+                    assert np.array_equal(r.pairs, sel) and np.array_equal(r.counts, cnt)
+                    assert np.array_equal(idx.degree(), d_union)
+                    seen_unchanged += 1
+    finally:
+        lib.tcrnet_debug_fail_alloc(-1)
+    assert seen_unchanged >= 1 and seen_failed >= 1
