@@ -11,8 +11,6 @@ Contents
              "Adjacency matrix", "Overview of network theory concepts")
   k1.c       an independent closed-form witness for threshold 1 (no DP)
   graph.c    breadth-first connected components and site percolation
-  workmodel.c  the benchmark's work model: text steps of the pair kernel's
-             traversal, replayed from the oracle's exit steps
   checks.py  pure-Python brute force over the edit graph on tiny alphabets
 
 ``build_lib()`` compiles the C files into ``liboracle.so`` with gcc.
@@ -27,8 +25,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
-SOURCES = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "k1.c"), os.path.join(_HERE, "graph.c"),
-           os.path.join(_HERE, "workmodel.c")]
+SOURCES = [os.path.join(_HERE, "oracle.c"), os.path.join(_HERE, "k1.c"), os.path.join(_HERE, "graph.c")]
 
 
 def build_lib(out: str = LIB_PATH, extra_flags=()) -> str:
@@ -69,9 +66,6 @@ def _bind(lib):
     lib.oracle_exit_steps.restype = None
     lib.oracle_exit_steps.argtypes = [_u8p, _u8p, _u8p, _u8p, ctypes.c_uint64, ctypes.c_int32, ctypes.c_int,
                                       ctypes.c_void_p]
-    lib.wm_items.restype = None
-    lib.wm_items.argtypes = [_u8p, _u8p, _u8p, _u8p, _u8p, ctypes.c_int64, ctypes.c_int, ctypes.c_int,
-                             ctypes.c_void_p, ctypes.c_void_p]
     lib.k1_build.restype = ctypes.c_int
     lib.k1_build.argtypes = [_u8p, _u8p, ctypes.c_uint32, ctypes.POINTER(ctypes.c_void_p),
                              ctypes.POINTER(ctypes.c_uint64), ctypes.c_void_p]
@@ -183,22 +177,6 @@ class Oracle:
         self.lib.oracle_exit_steps(chars.ctypes.data, seqs.offsets.ctypes.data, pi.ctypes.data, pj.ctypes.data,
                                    len(pi), k, self.nthreads, out.ctypes.data)
         return out[:len(pi)]
-
-    def work_items(self, seqs, seq, gend, items, k: int, resume: int = 0):
-        """Work model: (text steps, texts visited) of each work item
-        (rows of items: gbase, np, tb, te, tri, width over sorted positions,
-        width = patterns per item; seq: sorted position -> input id; gend:
-        n x 8 prefix-group ends; resume: steps a visited text can take over
-        from the previous one)."""
-        seq = np.ascontiguousarray(seq, dtype=np.uint32)
-        gend = np.ascontiguousarray(gend, dtype=np.uint32)
-        items = np.ascontiguousarray(items, dtype=np.uint32).reshape(-1, 6)
-        steps = np.zeros(max(1, len(items)), dtype=np.uint64)
-        texts = np.zeros(max(1, len(items)), dtype=np.uint64)
-        chars = np.ascontiguousarray(seqs.chars) if seqs.chars.size else np.zeros(1, np.uint8)
-        self.lib.wm_items(chars.ctypes.data, seqs.offsets.ctypes.data, seq.ctypes.data, gend.ctypes.data,
-                          items.ctypes.data, len(items), k, resume, steps.ctypes.data, texts.ctypes.data)
-        return steps[:len(items)], texts[:len(items)]
 
     def k1_build(self, seqs):
         """Closed-form threshold-1 network (no DP): edges, degree."""

@@ -63,7 +63,7 @@ def test_mutant_is_caught(tmp_path, name):
     assert src.count(old) == 1, f"mutation site for {name} not found exactly once"
     mut = tmp_path / "oracle.c"
     mut.write_text(src.replace(old, new))
-    others = [os.path.join(os.path.dirname(ORACLE_C), f) for f in ("k1.c", "graph.c", "workmodel.c")]
+    others = [os.path.join(os.path.dirname(ORACLE_C), f) for f in ("k1.c", "graph.c")]
     lib = tmp_path / "libmut.so"
     subprocess.run(["gcc", "-O1", "-std=c11", "-fopenmp", "-fPIC", "-shared", str(mut), *others, "-o", str(lib)],
                    check=True)

@@ -1,13 +1,13 @@
-"""The benchmark's work model (oracle/workmodel.c via oracle/workload_model.py):
-the prefix-group walk it replays is exact (every text a jump skips has no
-lane within k, checked against full DP distances), and the C replay matches
-a plain Python walk over the same items."""
+"""The benchmark's work model (workmodel/walk.c via workmodel/__init__.py):
+its own DP exit steps and distances equal the oracle's, the prefix-group
+walk it replays is exact (every text a jump skips has no lane within k,
+checked against the oracle's full DP distances), and the C replay matches a
+plain Python walk over the same items."""
 import numpy as np
 import pytest
 
-import oracle
-import oracle.workload_model as wm
 import synth
+import workmodel as wm
 
 
 def _setup(n, T, k, seed, pack=True):
@@ -38,7 +38,7 @@ def test_walk_is_exact_and_matches_python(orc, k, pack):
     s, L, order, gend, items = _setup(500, 128, k, 9 + k, pack)
     assert (items[:, 5] > wm.WAVE).any() == pack
     strs = s.to_list()
-    steps_c, texts_c = orc.work_items(s, order, gend, items, k, wm.RESUME)
+    steps_c, texts_c = wm.work_items(s, order, gend, items, k, wm.RESUME)
     skipped = 0
     for q, (gbase, npat, tb, te, tri, width) in enumerate(items.tolist()):
         steps = visited = 0
@@ -70,6 +70,21 @@ def test_walk_is_exact_and_matches_python(orc, k, pack):
             t = tn
         assert (steps, visited) == (int(steps_c[q]), int(texts_c[q]))
     assert skipped > 0
+
+
+@pytest.mark.parametrize("k", [0, 1, 2, 5])
+def test_model_exit_steps_equal_the_oracles(orc, k):
+    s = synth.repertoire(400, 40, 31 + k)
+    rng = np.random.default_rng(k)
+    pi = rng.integers(0, s.n, 3000)
+    pj = rng.integers(0, s.n, 3000)
+    got = wm.exit_steps(s, pi, pj, k)
+    want = orc.exit_steps(s, pi, pj, k)
+    assert np.array_equal(got, want)
+    strs = s.to_list()
+    for i, j in list(zip(pi, pj))[:300]:
+        e, lev = wm.exit_step(strs[i], strs[j], k)
+        assert e == orc.exit_step(strs[i], strs[j], k) and lev == orc.lev(strs[i], strs[j])
 
 
 def test_traversal_totals_small():

@@ -1,36 +1,109 @@
 """Algorithmic-work model of the named workloads -- writes ../bench_model.json.
 
-Test/benchmark infrastructure: it calls only ``oracle/`` and ``synth/``.
+Benchmark infrastructure: it prices the pair kernel's launches for the
+roofline; it decides no edge and imports neither the HIP library nor the
+test oracle (walk.c computes its own DP distances).
 
 For each workload it records
   * evaluated_pairs: pairs (i < j) with |len_i - len_j| <= k (the pairs the
     length filter keeps; counted from the length histogram);
   * mean_exit_steps: the mean, over a seeded uniform sample of those pairs,
     of the text steps the exact final-diagonal early exit needs (rows = the
-    longer string; computed from the oracle's full DP table, see
-    oracle_exit_step), with its standard error -- the per-pair work;
+    longer string; from a full DP table, see wm_exit_step), with its
+    standard error -- the per-pair work;
   * wave_steps: the text steps of the pair kernel's traversal, where a wave
     of 64 patterns walks the lexicographically sorted texts of a work item,
     jumps past every prefix group on which all its lanes ended early, and
     starts each visited text after the residues it shares with the previous
     one (up to RESUME of them)
-    (replayed by workmodel.c from the oracle's exit steps over a seeded
-    uniform sample of work items, or all items when few), with the number of
-    visited texts and the standard error.
+    (replayed by walk.c over a seeded uniform sample of work items, or all
+    items when few), with the number of visited texts and the standard error.
 The benchmark prices a build as wave_steps * 64 lanes * T_step.
 
-Usage: python -m oracle.workload_model [--samples 400000]
+Usage: python -m workmodel [--samples 400000]
 """
 from __future__ import annotations
 
 import argparse
+import ctypes
 import json
 import os
+import subprocess
 
 import numpy as np
 
-import oracle
 import synth
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libworkmodel.so")
+_lib = None
+
+
+def build_lib(out: str = LIB_PATH) -> str:
+    """Compile walk.c with gcc (OpenMP)."""
+    tmp = out + ".tmp"
+    subprocess.run(["gcc", "-O2", "-std=c11", "-fopenmp", "-fPIC", "-shared", os.path.join(_HERE, "walk.c"),
+                    "-o", tmp], check=True)
+    os.replace(tmp, out)
+    return out
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            build_lib()
+        lib = ctypes.CDLL(LIB_PATH)
+        vp = ctypes.c_void_p
+        lib.wm_exit_step.restype = ctypes.c_int
+        lib.wm_exit_step.argtypes = [vp, ctypes.c_int, vp, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_int)]
+        lib.wm_exit_steps.restype = None
+        lib.wm_exit_steps.argtypes = [vp, vp, vp, vp, ctypes.c_int64, ctypes.c_int, vp]
+        lib.wm_items.restype = None
+        lib.wm_items.argtypes = [vp, vp, vp, vp, vp, ctypes.c_int64, ctypes.c_int, ctypes.c_int, vp, vp]
+        _lib = lib
+    return _lib
+
+
+def _chars(seqs):
+    return np.ascontiguousarray(seqs.chars) if seqs.chars.size else np.zeros(1, np.uint8)
+
+
+def exit_step(a: str, b: str, k: int) -> tuple[int, int]:
+    """(exit step, distance) of one pair from the model's own DP table."""
+    a, b = a.encode(), b.encode()
+    lev = ctypes.c_int()
+    s = _load().wm_exit_step(a, len(a), b, len(b), k, ctypes.byref(lev))
+    return s, lev.value
+
+
+def exit_steps(seqs, pi, pj, k: int) -> np.ndarray:
+    pi = np.ascontiguousarray(pi, dtype=np.uint32)
+    pj = np.ascontiguousarray(pj, dtype=np.uint32)
+    out = np.zeros(max(1, len(pi)), dtype=np.int32)
+    chars = _chars(seqs)
+    offs = np.ascontiguousarray(seqs.offsets, dtype=np.uint64)
+    _load().wm_exit_steps(chars.ctypes.data, offs.ctypes.data, pi.ctypes.data, pj.ctypes.data, len(pi), k,
+                          out.ctypes.data)
+    return out[:len(pi)]
+
+
+def work_items(seqs, seq, gend, items, k: int, resume: int):
+    """(text steps, texts visited) of each work item (rows of items: gbase,
+    np, tb, te, tri, width over sorted positions; seq: sorted position ->
+    input id; gend: n x 8 prefix-group ends; resume: steps a visited text
+    can take over from the previous one)."""
+    seq = np.ascontiguousarray(seq, dtype=np.uint32)
+    gend = np.ascontiguousarray(gend, dtype=np.uint32)
+    items = np.ascontiguousarray(items, dtype=np.uint32).reshape(-1, 6)
+    steps = np.zeros(max(1, len(items)), dtype=np.uint64)
+    texts = np.zeros(max(1, len(items)), dtype=np.uint64)
+    chars = _chars(seqs)
+    offs = np.ascontiguousarray(seqs.offsets, dtype=np.uint64)
+    _load().wm_items(chars.ctypes.data, offs.ctypes.data, seq.ctypes.data, gend.ctypes.data, items.ctypes.data,
+                     len(items), k, resume, steps.ctypes.data, texts.ctypes.data)
+    return steps[:len(items)], texts[:len(items)]
+
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 OUT = os.path.join(ROOT, "bench_model.json")
@@ -212,7 +285,7 @@ def traversal(seqs, k: int, T: int, max_items: int, seed: int = 1, resume: int =
         pick = items
     else:
         pick = items[np.random.default_rng(seed).choice(total, size=max_items, replace=False)]
-    steps, texts = oracle.Oracle().work_items(seqs, order, gend, pick, k, resume)
+    steps, texts = work_items(seqs, order, gend, pick, k, resume)
     steps = steps.astype(np.float64)
     texts = texts.astype(np.float64)
     scale = total / max(1, len(pick))
@@ -229,7 +302,7 @@ def traversal(seqs, k: int, T: int, max_items: int, seed: int = 1, resume: int =
 def model(seqs, k: int, n_samples: int, seed: int = 1, T: int = 16384, max_items: int = 1 << 20) -> dict:
     lengths = seqs.lengths()
     pi, pj, evaluated = sample_pairs(lengths, k, n_samples, seed)
-    steps = oracle.Oracle().exit_steps(seqs, pi, pj, k).astype(np.float64)
+    steps = exit_steps(seqs, pi, pj, k).astype(np.float64)
     n = seqs.n
     return {
         "n": n,
@@ -248,7 +321,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--samples", type=int, default=400000)
     args = ap.parse_args()
-    out = {"note": "written by oracle/workload_model.py; exit steps from the oracle's full DP table; "
+    out = {"note": "written by workmodel (python -m workmodel); exit steps from a full DP table; "
                    "traversal = text steps of the sorted-text walk with prefix-group jumps",
            "workloads": {}}
     for name, (gen, k, T) in WORKLOADS.items():
