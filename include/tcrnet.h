@@ -143,6 +143,26 @@ TCRNET_API int32_t tcrnet_build_device(tcrnet_ctx* ctx, const char* d_data, cons
                                        uint32_t n, int32_t k, void* stream, uint32_t* d_pairs,
                                        uint64_t pair_capacity, int32_t* d_degree, uint64_t* n_edges);
 
+/* tcrnet_build_device for callers that cannot allocate device memory: code
+ * under HIP stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, result and errors as tcrnet_build_device, but
+ * the call allocates nothing (no device, pinned or library allocation): every
+ * intermediate buffer is carved from one static device array of
+ * TCRNET_NOALLOC_SCRATCH_BYTES per GPU, which each GPU the library runs on
+ * holds from the context's creation until the process ends.
+ *   Limit: the intermediate buffers of n sequences and pair_capacity edges
+ *   (about 232 bytes a sequence plus 25 bytes an edge slot, with the work
+ *   plan and sort state) must fit the array; otherwise the call returns
+ *   TCRNET_EINVAL before any device work, naming the bytes it would need.
+ *   Every call on one GPU shares that GPU's array and leaves its contents
+ *   behind (the call clears what must start at zero itself): calls that
+ *   overlap on one GPU, from any thread, context or stream, race and give
+ *   undefined results.  Serialise them. */
+#define TCRNET_NOALLOC_SCRATCH_BYTES (64u << 20)
+TCRNET_API int32_t tcrnet_build_device_noalloc(tcrnet_ctx* ctx, const char* d_data, const uint64_t* d_offsets,
+                                               uint32_t n, int32_t k, void* stream, uint32_t* d_pairs,
+                                               uint64_t pair_capacity, int32_t* d_degree, uint64_t* n_edges);
+
 /* Multi-threshold build: every pair with lev <= k_max, with its exact
  * distance (paper, Results, "LCC transition": networks for several l_max).
  * The network at any k <= k_max is the set of edges with distance <= k.

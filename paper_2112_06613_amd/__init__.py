@@ -77,6 +77,8 @@ _SIGS = [
     ("tcrnet_debug_fail_alloc", None, [ctypes.c_int64]),
     ("tcrnet_build", _I32, [_P, ctypes.POINTER(tcrnet_seqs), _I32, _PP]),
     ("tcrnet_build_device", _I32, [_P, _P, _P, ctypes.c_uint32, _I32, _P, _P, ctypes.c_uint64, _P, _U64P]),
+    ("tcrnet_build_device_noalloc", _I32, [_P, _P, _P, ctypes.c_uint32, _I32, _P, _P, ctypes.c_uint64, _P,
+                                           _U64P]),
     ("tcrnet_build_batch", _I32, [_P, ctypes.POINTER(tcrnet_seqs), ctypes.c_uint32, _I32, _PP]),
     ("tcrnet_graph_edges", _I32, [_P, _PP, _U64P]),
     ("tcrnet_graph_degree", _I32, [_P, _PP, _U32P]),
@@ -284,6 +286,30 @@ def tcrnet_build_device(ctx: Context, d_chars, d_offsets, k: int, d_pairs, d_deg
         raise err
     _check(rc)
     return ne.value
+
+
+def tcrnet_build_device_noalloc(ctx: Context, d_chars, d_offsets, k: int, d_pairs, d_degree,
+                                stream=None) -> int:
+    """tcrnet_build_device with every intermediate buffer in the library's
+    static per-GPU scratch array (the call allocates nothing).  Same
+    arguments, result and errors; TCRNET_EINVAL when the build does not fit
+    the array (NOALLOC_SCRATCH_BYTES)."""
+    n = d_offsets.numel() - 1
+    cap = d_pairs.shape[0] if d_pairs is not None else 0
+    st = stream.cuda_stream if stream is not None else None
+    ne = ctypes.c_uint64()
+    rc = _lib.tcrnet_build_device_noalloc(ctx.handle, d_chars.data_ptr(), d_offsets.data_ptr(), n, k, st,
+                                          d_pairs.data_ptr() if cap else None, cap, d_degree.data_ptr(),
+                                          ctypes.byref(ne))
+    if rc == TCRNET_ETRUNC:
+        err = TcrnetError(rc, _lib.tcrnet_last_error().decode())
+        err.n_edges = ne.value
+        raise err
+    _check(rc)
+    return ne.value
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # TCRNET_NOALLOC_SCRATCH_BYTES
 
 
 def tcrnet_build_batch(ctx: Context, reps, k: int) -> list[Graph]:

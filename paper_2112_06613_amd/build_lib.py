@@ -16,7 +16,7 @@ INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libtcrnet.so")
 
-SOURCES = ["prep.hip", "radix.hip", "pairs.hip", "post.hip", "graph.hip", "probe.hip", "pipeline.cpp", "api.cpp", "tune.cpp", "serve.cpp",
+SOURCES = ["prep.hip", "radix.hip", "pairs.hip", "post.hip", "graph.hip", "probe.hip", "pipeline.cpp", "api.cpp", "tune.cpp", "serve.cpp", "noalloc.hip",
            "analysis.cpp"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -169,6 +169,8 @@ int32_t tcrnet_ctx_create(int32_t device, const tcrnet_opts* opts, tcrnet_ctx** 
   if (strncmp(prop.gcnArchName, "gfx950", 6) != 0)
     return set_error(TCRNET_EDEVICE, "device %d is %s; this library is built for gfx950", device, prop.gcnArchName);
   if ((e = hipSetDevice(device)) != hipSuccess) return hip_error(e, "hipSetDevice");
+  // this device's copy of the static scratch of tcrnet_build_device_noalloc
+  if ((e = scratch_attach(device)) != hipSuccess) return hip_error(e, "static scratch lookup");
   tcrnet_ctx* c = new tcrnet_ctx();
   c->device = device;
   snprintf(c->arch, sizeof c->arch, "%s", prop.gcnArchName);

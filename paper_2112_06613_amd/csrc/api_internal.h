@@ -81,6 +81,9 @@ Sched pick_sched(const tcrnet_ctx* ctx, uint64_t n, int k, int form = kFormPlain
 int32_t batch_upload(tcrnet_ctx* ctx, const tcrnet_seqs* reps, uint32_t n_reps, BatchInput* bi);
 int32_t batch_launch(tcrnet_ctx* ctx, const BatchInput& bi, int32_t k, const Sched& sched, uint64_t* E,
                      tcrnet_build_info* info);
+// Find this device's copy of the static scratch array of the allocation-free
+// build (once per device, with the device current).
+hipError_t scratch_attach(int device);
 int32_t check_k(int32_t k);
 int32_t check_host_seqs(const tcrnet_seqs* s, const char* what);
 int32_t run_pipeline(tcrnet_ctx* ctx, Pipeline& pl, PipeParams pp, hipStream_t st, bool grow_ok,

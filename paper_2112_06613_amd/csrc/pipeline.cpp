@@ -74,34 +74,51 @@ uint32_t bits_for(uint64_t v) {
 
 static uint32_t seg_bits_for(uint32_t n_seg) { return n_seg <= 1 ? 0 : bits_for(n_seg); }
 
-hipError_t pipeline_reserve(Pipeline& pl, uint64_t n, uint32_t n_seg, int k, uint32_t T, uint64_t capacity,
-                            uint32_t max_desc) {
+void pipeline_buffers(Pipeline& pl, DevBuf* bufs[kPipeBufs]) {
+  DevBuf* b[kPipeBufs] = {&pl.rec,   &pl.key,   &pl.key2,  &pl.val,  &pl.val2,  &pl.srec,  &pl.speq,  &pl.off,
+                          &pl.descs, &pl.ibase, &pl.meta,  &pl.tmp,  &pl.edges, &pl.edist, &pl.ekeys, &pl.ekeys2};
+  for (int i = 0; i < kPipeBufs; ++i) bufs[i] = b[i];
+}
+
+void pipeline_sizes(uint64_t n, uint32_t n_seg, int k, uint32_t T, uint64_t capacity, uint32_t max_desc,
+                    size_t bytes[kPipeBufs], uint32_t* max_desc_out) {
   const uint64_t nn = n ? n : 1;
   if (!max_desc) max_desc = plan_max_desc_self(n_seg, k, T, n);
   const uint64_t cap = capacity ? capacity : 1;
-  hipError_t e;
-#define TCR_RESERVE(buf, bytes) \
-  if ((e = (buf).ensure(bytes)) != hipSuccess) return e;
-  TCR_RESERVE(pl.rec, nn * sizeof(SeqRec));
-  TCR_RESERVE(pl.key, nn * 8);
-  TCR_RESERVE(pl.key2, nn * 8);
-  TCR_RESERVE(pl.val, nn * 4);
-  TCR_RESERVE(pl.val2, nn * 4);
-  TCR_RESERVE(pl.srec, nn * sizeof(SeqRec));
-  TCR_RESERVE(pl.speq, nn * sizeof(PeqRec));
-  TCR_RESERVE(pl.off, ((uint64_t)n_seg * 64 + 1) * 4);
-  TCR_RESERVE(pl.descs, (uint64_t)max_desc * sizeof(Desc));
-  TCR_RESERVE(pl.ibase, (uint64_t)max_desc * 8);
-  TCR_RESERVE(pl.meta, sizeof(Counters) + sizeof(Plan) + 64);
-  const uint64_t tw = radix_tmp_words(nn > cap ? nn : cap);
-  TCR_RESERVE(pl.tmp, tw * 4);
-  TCR_RESERVE(pl.edges, cap * 8);
-  TCR_RESERVE(pl.edist, cap);
-  TCR_RESERVE(pl.ekeys, cap * 8);
-  TCR_RESERVE(pl.ekeys2, cap * 8);
-#undef TCR_RESERVE
-  pl.n_cap = nn;
-  pl.e_cap = cap;
+  const size_t b[kPipeBufs] = {
+      nn * sizeof(SeqRec),                          // rec
+      nn * 8,                                       // key
+      nn * 8,                                       // key2
+      nn * 4,                                       // val
+      nn * 4,                                       // val2
+      nn * sizeof(SeqRec),                          // srec
+      nn * sizeof(PeqRec),                          // speq
+      ((uint64_t)n_seg * 64 + 1) * 4,               // off
+      (uint64_t)max_desc * sizeof(Desc),            // descs
+      (uint64_t)max_desc * 8,                       // ibase
+      sizeof(Counters) + sizeof(Plan) + 64,         // meta
+      radix_tmp_words(nn > cap ? nn : cap) * 4,     // tmp
+      cap * 8,                                      // edges
+      cap,                                          // edist
+      cap * 8,                                      // ekeys
+      cap * 8,                                      // ekeys2
+  };
+  for (int i = 0; i < kPipeBufs; ++i) bytes[i] = b[i];
+  *max_desc_out = max_desc;
+}
+
+hipError_t pipeline_reserve(Pipeline& pl, uint64_t n, uint32_t n_seg, int k, uint32_t T, uint64_t capacity,
+                            uint32_t max_desc) {
+  size_t bytes[kPipeBufs];
+  DevBuf* bufs[kPipeBufs];
+  pipeline_sizes(n, n_seg, k, T, capacity, max_desc, bytes, &max_desc);
+  pipeline_buffers(pl, bufs);
+  for (int i = 0; i < kPipeBufs; ++i) {
+    const hipError_t e = bufs[i]->ensure(bytes[i]);
+    if (e != hipSuccess) return e;
+  }
+  pl.n_cap = n ? n : 1;
+  pl.e_cap = capacity ? capacity : 1;
   pl.desc_cap = max_desc;
   return hipSuccess;
 }

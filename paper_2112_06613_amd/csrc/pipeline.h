@@ -15,21 +15,31 @@ hipError_t dev_malloc(void** p, size_t bytes);
 hipError_t host_malloc(void** p, size_t bytes);
 void arm_alloc_failure(int64_t after);  // -1: disarm
 
-// Grow-only device buffer.
+// Grow-only device buffer, or a borrowed view of memory the buffer does not
+// own (never freed, never grown).
 struct DevBuf {
   void* p = nullptr;
   size_t cap = 0;
+  bool borrowed = false;
   DevBuf() = default;
   DevBuf(const DevBuf&) = delete;
   DevBuf& operator=(const DevBuf&) = delete;
   ~DevBuf() { release(); }
   void release() {
-    if (p) (void)hipFree(p);
+    if (p && !borrowed) (void)hipFree(p);
     p = nullptr;
     cap = 0;
+    borrowed = false;
+  }
+  void borrow(void* q, size_t bytes) {
+    release();
+    p = q;
+    cap = bytes;
+    borrowed = true;
   }
   hipError_t ensure(size_t bytes) {
     if (bytes <= cap && p) return hipSuccess;
+    if (borrowed) return hipErrorOutOfMemory;
     release();
     const size_t nb = bytes < 256 ? 256 : bytes + bytes / 8;
     hipError_t e = dev_malloc(&p, nb);
@@ -96,8 +106,15 @@ struct PipeParams {
 
 uint32_t bits_for(uint64_t v);  // number of bits to hold values < v (>= 1)
 
-// Allocate every buffer the pipeline needs for these sizes (max_desc: 0 =
-// the bound of a self plan over n sequences in n_seg segments).
+// Bytes of each pipeline buffer for these sizes, in the order of
+// pipeline_buffers() (max_desc: 0 = the bound of a self plan over n
+// sequences in n_seg segments).
+constexpr int kPipeBufs = 16;
+void pipeline_sizes(uint64_t n, uint32_t n_seg, int k, uint32_t T, uint64_t capacity, uint32_t max_desc,
+                    size_t bytes[kPipeBufs], uint32_t* max_desc_out);
+void pipeline_buffers(Pipeline& pl, DevBuf* bufs[kPipeBufs]);
+
+// Allocate every buffer the pipeline needs for these sizes.
 hipError_t pipeline_reserve(Pipeline& pl, uint64_t n, uint32_t n_seg, int k, uint32_t T, uint64_t capacity,
                             uint32_t max_desc = 0);
 
