@@ -102,6 +102,10 @@ typedef struct {
                                      residues (default: two, in 16-bit halves) */
 #define TCRNET_F_PEQ_VGPR 8u      /* keep pattern bit masks in VGPRs (default for
                                      smaller builds and for serving) */
+#define TCRNET_F_COUNT_WORK 16u   /* run the pair kernel's counting variant: the
+                                     same walk, also counting visited texts and
+                                     wave text steps (tcrnet_build_info); slower,
+                                     for measurement only */
 
 /* Create a context on HIP device `device` (stream, workspace, options).
    Fails with TCRNET_EDEVICE if the device is absent or not gfx950. */
@@ -201,6 +205,11 @@ typedef struct {
   uint32_t graph_captured; /* batched builds: 1 if this call captured a new
                               HIP graph (first call, or a changed shape or
                               buffer), 0 if it replayed the previous one */
+  uint32_t work_counted;   /* 1: the three counts below are valid
+                              (TCRNET_F_COUNT_WORK) */
+  uint64_t visited_texts;  /* texts the pair kernel's walk visited */
+  uint64_t wave_steps;     /* wave text steps (Myers/Hyyro steps of a wave) */
+  uint64_t wave_steps_packed; /* of which with two patterns per lane */
 } tcrnet_build_info;
 TCRNET_API int32_t tcrnet_graph_info(const tcrnet_graph* g, tcrnet_build_info* info);
 /* Counters of the context's most recent build of any kind. */

@@ -21,6 +21,7 @@ TCRNET_F_NO_AUTOTUNE = 1
 TCRNET_F_PEQ_LDS = 2
 TCRNET_F_NO_PACK = 4
 TCRNET_F_PEQ_VGPR = 8
+TCRNET_F_COUNT_WORK = 16
 MAX_LEN = 32
 MAX_K = 31
 
@@ -53,7 +54,9 @@ class tcrnet_build_info(ctypes.Structure):
                 ("build_ms", ctypes.c_double), ("pair_launches", ctypes.c_uint32),
                 ("texts_per_item", ctypes.c_uint32), ("waves_per_simd", ctypes.c_uint32),
                 ("peq_lds", ctypes.c_uint32),
-                ("pack", ctypes.c_uint32), ("tuned", ctypes.c_uint32), ("graph_captured", ctypes.c_uint32)]
+                ("pack", ctypes.c_uint32), ("tuned", ctypes.c_uint32), ("graph_captured", ctypes.c_uint32),
+                ("work_counted", ctypes.c_uint32), ("visited_texts", ctypes.c_uint64),
+                ("wave_steps", ctypes.c_uint64), ("wave_steps_packed", ctypes.c_uint64)]
 
 
 class tcrnet_result_info(ctypes.Structure):

@@ -89,10 +89,20 @@ Sched pick_sched(const tcrnet_ctx* ctx, uint64_t n, int k, int form) {
   if (ctx->opts.flags & TCRNET_F_PEQ_LDS) s.peq_lds = true;
   if (ctx->opts.flags & TCRNET_F_PEQ_VGPR) s.peq_lds = false;
   if (ctx->opts.flags & TCRNET_F_NO_PACK) s.pack = false;
+  s.count_work = (ctx->opts.flags & TCRNET_F_COUNT_WORK) != 0;
   // whole waves of 64 texts per item keep triangle items non-empty
   s.texts_per_item = std::max<uint32_t>(64, (s.texts_per_item + 63) / 64 * 64);
   s.waves_per_simd = std::min<uint32_t>(8, std::max<uint32_t>(1, s.waves_per_simd));
   return s;
+}
+
+// Work counts of the pair kernel's counting variant into a build's info.
+void note_work(const Sched& sched, const Meta& m, tcrnet_build_info* inf) {
+  if (!sched.count_work) return;
+  inf->work_counted = 1;
+  inf->visited_texts = m.cnt.visits;
+  inf->wave_steps = m.cnt.steps;
+  inf->wave_steps_packed = m.cnt.steps_packed;
 }
 
 // Run one pipeline on device-resident input into (d_pairs, d_deg) with
@@ -139,6 +149,7 @@ int32_t run_pipeline(tcrnet_ctx* ctx, Pipeline& pl, PipeParams pp, hipStream_t s
     inf.build_ms += bt;
     inf.pair_launches += 1;
     inf.evaluated_pairs = m.plan.evaluated_pairs;
+    note_work(sched, m, &inf);
     if (m.cnt.fault) return set_error(TCRNET_EDEVICE, "device sort stalled (internal)");
     if (m.cnt.err != kNoError) return set_error(TCRNET_EINVAL, "%s", input_error_message(m.cnt.err).c_str());
     if (m.plan.pad) return set_error(TCRNET_EDEVICE, "work plan overflow (internal)");
@@ -501,6 +512,7 @@ int32_t batch_launch(tcrnet_ctx* ctx, const BatchInput& bi, int32_t k, const Sch
       key.W = sched.waves_per_simd;
       key.lds = sched.peq_lds;
       key.pack = sched.pack;
+      key.count = sched.count_work;
       key.capacity = pp.capacity;
       key.desc_cap = ctx->pipe.desc_cap;
       {
@@ -541,6 +553,7 @@ int32_t batch_launch(tcrnet_ctx* ctx, const BatchInput& bi, int32_t k, const Sch
       info.build_ms += bt;
       info.pair_launches += 1;
       info.evaluated_pairs = m.plan.evaluated_pairs;
+      note_work(sched, m, &info);
       if (m.cnt.fault) return set_error(TCRNET_EDEVICE, "device sort stalled (internal)");
       if (m.cnt.err != kNoError) {
         const std::vector<uint32_t>& seg = bi.seg;

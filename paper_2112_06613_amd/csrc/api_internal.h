@@ -17,12 +17,12 @@ struct BatchKey {
   uint32_t n = 0, n_seg = 0;
   int k = 0;
   uint32_t T = 0, W = 0;
-  bool lds = false, pack = false;
+  bool lds = false, pack = false, count = false;
   uint64_t capacity = 0;
   uint32_t desc_cap = 0;
   std::vector<std::pair<const void*, size_t>> bufs;
   bool operator==(const BatchKey& o) const {
-    return n == o.n && n_seg == o.n_seg && k == o.k && T == o.T && W == o.W && lds == o.lds && pack == o.pack &&
+    return n == o.n && n_seg == o.n_seg && k == o.k && T == o.T && W == o.W && lds == o.lds && pack == o.pack && count == o.count &&
            capacity == o.capacity && desc_cap == o.desc_cap && bufs == o.bufs;
   }
 };
@@ -84,6 +84,7 @@ int32_t batch_launch(tcrnet_ctx* ctx, const BatchInput& bi, int32_t k, const Sch
 // Find this device's copy of the static scratch array of the allocation-free
 // build (once per device, with the device current).
 hipError_t scratch_attach(int device);
+void note_work(const Sched& sched, const Meta& m, tcrnet_build_info* inf);
 int32_t check_k(int32_t k);
 int32_t check_host_seqs(const tcrnet_seqs* s, const char* what);
 int32_t run_pipeline(tcrnet_ctx* ctx, Pipeline& pl, PipeParams pp, hipStream_t st, bool grow_ok,

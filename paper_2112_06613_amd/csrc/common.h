@@ -112,7 +112,10 @@ struct alignas(256) Counters {
                                   // code 1: residue outside the alphabet,
                                   // code 2: length 0 or > 32; ~0: none
   unsigned long long fault;       // nonzero: a device sort pass stalled
-  unsigned long long pad1[13];
+  // work of the pair kernel's counting variant: visited texts, wave text
+  // steps, and the steps with two patterns per lane among them
+  unsigned long long visits, steps, steps_packed;
+  unsigned long long pad1[10];
 };
 constexpr unsigned long long kNoError = ~0ull;
 

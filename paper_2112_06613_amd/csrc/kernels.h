@@ -78,6 +78,7 @@ struct PairArgs {
   uint64_t capacity;
   uint32_t texts_per_item;
   int32_t k;
+  bool count_work = false;  // run the counting variant (Counters::visits/steps)
 };
 void launch_pairs(const PairArgs& a, uint32_t grid_blocks, bool peq_lds, hipStream_t st);
 uint32_t pair_grid_blocks(int device, uint32_t waves_per_simd);

@@ -140,21 +140,27 @@ __device__ __forceinline__ bool within_k_lane(uint32_t z, int k) {
   }
 }
 
-// Where a text's step chain ended (wave-uniform): ex = the step after which
-// no lane was within k (32: every step ran), tn = the next text to visit,
-// lcp = the steps that text reuses.
-struct StepExit {
-  uint32_t ex, tn, lcp;
-};
-
 template <int V>
 struct Tag {
   static constexpr int value = V;
 };
 
+// Depth of the walk's sibling loops: residues 0 .. kLoopDepth-1 of a text are
+// stepped one prefix-tree level at a time (every sibling group of a level in
+// its own loop iteration, the parent's state resident in registers); texts
+// that are still alive after kLoopDepth residues run the rest of their steps
+// one text at a time.  Must not exceed kSkipDepths (the group ends a record
+// holds).
+constexpr int kLoopDepth = 6;
+static_assert(kLoopDepth <= kSkipDepths, "a sibling loop needs the group end of its depth");
+
+// Byte offset of the id field in a SeqRec.
+constexpr uint32_t kRecIdOff = 28;
+
 // kMode: the within-k test on the miss word: 1 (k = 1), 2 (k = 2), 0 (any k:
-// popcount).
-template <bool kPeqLds, int kMode>
+// popcount).  kCount: also count visited texts and wave text steps (the
+// work-counting variant; the traversal is the same).
+template <bool kPeqLds, int kMode, bool kCount>
 __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs,
                                                   const uint64_t* __restrict__ item_base,
                                                   const Plan* __restrict__ plan, Counters* __restrict__ cnt,
@@ -174,6 +180,8 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
   uint2* wave_edge = lds_edge[wid];
   uint8_t* wave_dist = lds_dist[wid];
   uint32_t staged = 0;  // edges in wave_edge (wave-uniform)
+  // work counters of the counting variant (wave-uniform)
+  uint32_t n_visits = 0, n_steps = 0, n_steps_packed = 0;
 
   // Move the staged edges to consecutive global slots (one atomic per wave).
   auto flush = [&]() {
@@ -250,51 +258,48 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     // after them in the item (those patterns are masked off)
     const uint32_t tri_end = d.tri ? gbase + kGroup : 0u;
     const SeqRec* tbase = trec + tb0;  // this item's text records
+    auto rec_at = [&](uint32_t t) { return load_const_at<SeqRec>(tbase, (t - tb0) * (uint32_t)sizeof(SeqRec)); };
 
-    // Register stack of the state after each of the first kDepth text steps.
-    // Texts are visited in sorted order, so a text sharing its first r
-    // residues with the previous visited text resumes at step r from the
-    // stored state (a depth-first walk over the implicit prefix tree of the
-    // sorted texts); r = 0 for an item's first text and whenever the set of
-    // valid lanes changes.
-    constexpr int kDepth = 6;
-    uint32_t sVP[kDepth], sVN[kDepth], sZ[kDepth];
-    uint32_t r = 0;
-
-    uint32_t t = tb;
-    // The texts are walked in two runs, each with its own copy of the loop:
-    // first the ragged ones (in a triangle item, texts before tri_end, where
-    // the set of valid patterns still grows with the next texts, so neither
-    // jumps nor resumed state apply and later patterns are masked), then
-    // the rest, whose loop carries none of that per-text bookkeeping.
-    auto walk = [&](auto rag_tag, uint32_t t_end) {
-    constexpr bool kRagged = decltype(rag_tag)::value;
-    while (t < t_end) {
-      // the whole record (codes, length, id, group ends): one scalar load
-      const SeqRec tr = load_const_at<SeqRec>(tbase, (t - tb0) * (uint32_t)sizeof(SeqRec));
-      uint32_t z_text = z_item;
-      if constexpr (kRagged) {  // patterns not before the text are masked
-        const uint32_t dt = t - gbase;
-        if constexpr (kPack == 2) {
-          if (lane >= dt) z_text |= 0xFFFFu;
-          if (lane + kWave >= dt) z_text |= 0xFFFF0000u;
-        } else {
-          if (lane >= dt) z_text = ~0u;
+    // Edges of the patterns whose final miss word fZ is within k, against
+    // every text of [t_first, t_end) (a run of identical texts).
+    auto emit = [&](uint32_t fZ, uint32_t t_first, uint32_t t_end) {
+      const uint32_t fz0 = kPack == 2 ? fZ & 0xFFFFu : fZ;
+      const bool hit0 = within_k_word<kMode>(fz0, k);
+      const bool hit1 = kPack == 2 && within_k_word<kMode>(fZ >> 16, k);
+      const uint64_t hm0 = __ballot(hit0);
+      const uint64_t hm1 = kPack == 2 ? __ballot(hit1) : 0ull;
+      if (!(hm0 | hm1)) return;
+      const uint32_t nh0 = (uint32_t)__popcll(hm0);
+      const uint32_t nh = nh0 + (uint32_t)__popcll(hm1);
+      const uint32_t* pid = reinterpret_cast<const uint32_t*>(prec);  // ids: word 7 of a record
+      const uint32_t id0 = hit0 ? load_global(pid, 16 * p0 + 7) : 0u;  // pattern ids, read on a hit only
+      const uint32_t id1 = hit1 ? load_global(pid, 16 * p1 + 7) : 0u;
+      for (uint32_t u = t_first; u < t_end; ++u) {
+        const uint32_t tid = load_const_at<uint32_t>(tbase, (u - tb0) * (uint32_t)sizeof(SeqRec) + kRecIdOff);
+        if (staged + nh > (uint32_t)kEdgeBuf) flush();
+        if (hit0) {
+          const uint32_t pos = staged + (uint32_t)__popcll(hm0 & lt_mask);
+          wave_edge[pos] = make_uint2(id0, tid);
+          wave_dist[pos] = (uint8_t)__popc(fz0);
         }
+        if (hit1) {
+          const uint32_t pos = staged + nh0 + (uint32_t)__popcll(hm1 & lt_mask);
+          wave_edge[pos] = make_uint2(id1, tid);
+          wave_dist[pos] = (uint8_t)__popc(fZ >> 16);
+        }
+        staged += nh;
       }
-      // per-text copy of the length the compiler cannot see through, so that
-      // the per-step length tests are formed inside the loop instead of being
-      // hoisted into (spilled) registers
-      uint32_t nn = n;
-      asm volatile("" : "+s"(nn));
+      if constexpr (kCount) n_visits += t_end - t_first - 1;  // the identical texts after the first
+    };
 
-// One Myers/Hyyro text step on character J, then the miss accounting: OR the
-// diagonal row's miss bit into Z; alive: some lane still within k.
+// One Myers/Hyyro text step on residue J of record `rec` from the state
+// (VP, VN, Z), then the miss accounting: OR the diagonal row's miss bit
+// (mj) into Z; alive: some lane still within k.
 #define TCR_EQ(cc) (kPeqLds ? wave_eq[(cc) * kWave + lane] : eq[(cc)])
-#define TCR_CODE(q) ((tr.w[(q) / 6] >> (5 * ((q) % 6))) & 31u)
-#define TCR_CORE(J)                                                            \
+#define TCR_CODE(rr, q) (((rr).w[(q) / 6] >> (5 * ((q) % 6))) & 31u)
+#define TCR_STEP(rr, J, mj)                                                    \
   {                                                                            \
-    const uint32_t Eq = TCR_EQ(TCR_CODE(J));                                   \
+    const uint32_t Eq = TCR_EQ(TCR_CODE(rr, J));                               \
     uint32_t D0;                                                               \
     if constexpr (kPack == 2) {                                                \
       D0 = (pk_add(Eq & VP, VP) ^ VP) | Eq | VN;                               \
@@ -311,81 +316,46 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
       VN = X & D0;                                                             \
       VP = twice(HN) | ~(X | D0);                                              \
     }                                                                          \
-    Z |= ~D0 & mJ;                                                             \
-    mJ = twice(mJ);                                                            \
+    Z |= ~D0 & (mj);                                                           \
     alive = __ballot((within_k_lane<kMode, kPack>(Z, k))) != 0ull;             \
-  }
-#define TCR_SLOT(J) ((J) < kDepth ? (J) : 0)
-// Text steps are nested ifs (structured control flow, so every exit stays a
-// plain scalar or VCC branch): step J runs only while J < n and some lane is
-// still within k; a wave with none left records the step in ex.  Steps below
-// kDepth take their input from stack slot J-1 (or the first column) and keep
-// their output in slot J, unless reused from the previous text (J < r): in
-// the copy of the chain entered at depth kStart, steps below kStart are
-// reused without a test and steps from kStart up to kNext - 2 test J >= r.
-#define TCR_OPEN(J)                                                            \
-  if ((J) < kStart || (uint32_t)(J) < nn) {                                    \
-    if constexpr ((J) < kDepth) {                                              \
-      if ((J) >= kNext - 1 || ((J) >= kStart && (kRagged || (uint32_t)(J) >= rr))) { \
-        if constexpr ((J) > 0) {                                               \
-          VP = sVP[TCR_SLOT((J) - 1)];                                         \
-          VN = sVN[TCR_SLOT((J) - 1)];                                         \
-          Z = sZ[TCR_SLOT((J) - 1)];                                           \
-        }                                                                      \
-        TCR_CORE(J)                                                            \
-        sVP[TCR_SLOT(J)] = VP;                                                 \
-        sVN[TCR_SLOT(J)] = VN;                                                 \
-        sZ[TCR_SLOT(J)] = Z;                                                   \
-      }                                                                        \
-    } else {                                                                   \
-      if constexpr ((J) == kDepth) {                                           \
-        VP = sVP[kDepth - 1];                                                  \
-        VN = sVN[kDepth - 1];                                                  \
-        Z = sZ[kDepth - 1];                                                    \
-      }                                                                        \
-      TCR_CORE(J)                                                              \
-    }                                                                          \
-    if (alive) {
-// A wave with no lane within k after step J < 8 jumps: every text sharing
-// this text's first J+1 residues ends the same way, so the walk continues at
-// the end of that prefix group (nxt[J]; the record's own prefix length with
-// it is the state the next text reuses).
-#define TCR_CLOSE(J)                                                           \
-    } else {                                                                   \
-      ex = (J);                                                                \
-      if constexpr ((J) < kSkipDepths && !kRagged) {                           \
-        tn = max(tr.nxt[(J)], t + 1);                                          \
-        lcp_next = (J) == 0 ? 0u : (tr.len >> (10 + 3 * ((J) - 1))) & 7u;      \
-      } else {                                                                 \
-        lcp_next = (tr.len >> 6) & 15u;                                        \
-      }                                                                        \
+    if constexpr (kCount) {                                                    \
+      ++n_steps;                                                               \
+      if constexpr (kPack == 2) ++n_steps_packed;                              \
     }                                                                          \
   }
 
-      // The step chain exists in one copy per entry depth kStart, serving
-      // resume depths r in [kStart, kNext): the resumed steps of a text cost
-      // no tests, where testing each one again costs about 9 scalar and
-      // branch instructions.  Entry depths 0, 4, 5 and 6: each copy adds
-      // registers, and these four keep the kernel within 96 VGPRs with the
-      // masks in VGPRs (five waves per SIMD) and within 80 with them in LDS
-      // (six).  The exit state comes back by value, the (per-lane) miss word
-      // through a reference, so the uniform values stay in scalar registers.
-      uint32_t rr = r;
-      asm volatile("" : "+s"(rr));
-      uint32_t Z;  // the miss word after the last computed step
-      auto chain = [&](auto start_tag, auto next_tag, uint32_t& z_out) __attribute__((always_inline)) {
+    // The rest of one text's steps, kStart .. n-1, from the state (VP, VN,
+    // Z) after kStart residues; stops after the step at which no lane is
+    // within k.  Returns the exit (the step index, or 32 when all n steps ran)
+    // and the next text to visit: after an exit at J < kSkipDepths (and not
+    // in the ragged run) the end of the text's depth-(J+1) prefix group --
+    // every text sharing those J+1 residues ends the same way --, else t + 1.
+    // The steps are nested ifs (structured control flow: every exit is a
+    // plain scalar or VCC branch); a per-text copy of the length that the
+    // compiler cannot see through keeps the per-step tests from being hoisted
+    // into registers.
+    auto chain = [&](auto start_tag, auto rag_tag, const SeqRec& rec, uint32_t t, uint32_t VP, uint32_t VN,
+                     uint32_t& Z) __attribute__((always_inline)) {
       constexpr int kStart = decltype(start_tag)::value;
-      constexpr int kNext = decltype(next_tag)::value;
-      uint32_t tn = t + 1;  // next text
-      // common prefix of this text with the next visited one (from the
-      // record's packed lengths): the steps the next text can reuse
-      uint32_t lcp_next = 0;
-      uint32_t ex = 32;  // text step after which no lane was within k (32: none)
-      uint32_t mJ = m_item << (kRagged ? 0u : rr);  // diagonal row bit(s) of the first computed step
+      constexpr bool kRagged = decltype(rag_tag)::value;
+      uint32_t nn = n;
+      asm volatile("" : "+s"(nn));
+      uint32_t ex = 32, tn = t + 1;
       bool alive = true;
-      uint32_t VP = Mm, VN = 0;
-      uint32_t& Z = z_out;
-      Z = z_text;
+      uint32_t mj = m_item << kStart;
+#define TCR_OPEN(J)                                                            \
+  if ((J) < kStart || (uint32_t)(J) < nn) {                                    \
+    if constexpr ((J) >= kStart) {                                             \
+      TCR_STEP(rec, J, mj)                                                     \
+      mj = twice(mj);                                                          \
+    }                                                                          \
+    if ((J) < kStart || alive) {
+#define TCR_CLOSE(J)                                                           \
+    } else {                                                                   \
+      ex = (J);                                                                \
+      if constexpr ((J) < kSkipDepths && !kRagged) tn = max(rec.nxt[(J)], t + 1); \
+    }                                                                          \
+  }
       TCR_OPEN(0) TCR_OPEN(1) TCR_OPEN(2) TCR_OPEN(3) TCR_OPEN(4) TCR_OPEN(5) TCR_OPEN(6) TCR_OPEN(7)
       TCR_OPEN(8) TCR_OPEN(9) TCR_OPEN(10) TCR_OPEN(11) TCR_OPEN(12) TCR_OPEN(13) TCR_OPEN(14)
       TCR_OPEN(15) TCR_OPEN(16) TCR_OPEN(17) TCR_OPEN(18) TCR_OPEN(19) TCR_OPEN(20) TCR_OPEN(21)
@@ -397,71 +367,102 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
       TCR_CLOSE(13) TCR_CLOSE(12) TCR_CLOSE(11) TCR_CLOSE(10) TCR_CLOSE(9) TCR_CLOSE(8)
       TCR_CLOSE(7) TCR_CLOSE(6) TCR_CLOSE(5) TCR_CLOSE(4) TCR_CLOSE(3) TCR_CLOSE(2) TCR_CLOSE(1)
       TCR_CLOSE(0)
-      return StepExit{ex, tn, lcp_next};
-      };
-      static_assert(kDepth == 6, "the entry depths cover resume depths 0..6");
-      StepExit x;
-      if constexpr (kRagged) {
-        x = chain(Tag<0>{}, Tag<1>{}, Z);
-      } else {
-        if (rr < 4) x = chain(Tag<0>{}, Tag<4>{}, Z);
-        else if (rr < 5) x = chain(Tag<4>{}, Tag<5>{}, Z);
-        else if (rr < 6) x = chain(Tag<5>{}, Tag<6>{}, Z);
-        else x = chain(Tag<6>{}, Tag<7>{}, Z);
-      }
-      const uint32_t ex = x.ex, tn = x.tn;
-      uint32_t lcp_next = x.lcp;
-
-      if (ex == 32) {
-        lcp_next = (tr.len >> 6) & 15u;
-        // all n steps ran: the state after step n-1 (stack slot or rolling)
-        uint32_t fZ = Z;
-#pragma unroll
-        for (int q = 0; q < kDepth; ++q)
-          if (n == (uint32_t)q + 1) fZ = sZ[q];
-        // patterns whose final distance D[m][n] = popcount is within k
-        const uint32_t fz0 = kPack == 2 ? fZ & 0xFFFFu : fZ;
-        const bool hit0 = within_k_word<kMode>(fz0, k);
-        const bool hit1 = kPack == 2 && within_k_word<kMode>(fZ >> 16, k);
-        const uint64_t hm0 = __ballot(hit0);
-        const uint64_t hm1 = kPack == 2 ? __ballot(hit1) : 0ull;
-        if (hm0 | hm1) {
-          const uint32_t nh0 = (uint32_t)__popcll(hm0);
-          const uint32_t nh = nh0 + (uint32_t)__popcll(hm1);
-          if (staged + nh > (uint32_t)kEdgeBuf) flush();
-          const uint32_t* pid = reinterpret_cast<const uint32_t*>(prec);  // ids: word 7 of a record
-          if (hit0) {
-            const uint32_t pos = staged + (uint32_t)__popcll(hm0 & lt_mask);
-            uint2 e;
-            e.x = load_global(pid, 16 * p0 + 7);  // pattern id, read on a hit only
-            e.y = tr.id;
-            wave_edge[pos] = e;
-            wave_dist[pos] = (uint8_t)__popc(fz0);
-          }
-          if (hit1) {
-            const uint32_t pos = staged + nh0 + (uint32_t)__popcll(hm1 & lt_mask);
-            uint2 e;
-            e.x = load_global(pid, 16 * p1 + 7);
-            e.y = tr.id;
-            wave_edge[pos] = e;
-            wave_dist[pos] = (uint8_t)__popc(fZ >> 16);
-          }
-          staged += nh;
-        }
-      }
-      r = kRagged ? 0u : min(lcp_next, (uint32_t)kDepth);
-      t = tn;
 #undef TCR_OPEN
 #undef TCR_CLOSE
-#undef TCR_SLOT
-#undef TCR_CORE
+      return uint2{ex, tn};
+    };
+
+    // Texts of [t, t_end), all sharing their first kLoopDepth residues, one at
+    // a time from the shared state after those residues.
+    auto leaf = [&](uint32_t sVP, uint32_t sVN, uint32_t sZ, uint32_t t, uint32_t t_end)
+                    __attribute__((always_inline)) {
+      SeqRec rec = rec_at(t);
+      for (;;) {
+        uint32_t Z = sZ;
+        const uint2 x = chain(Tag<kLoopDepth>{}, Tag<false>{}, rec, t, sVP, sVN, Z);
+        if (x.x == 32) emit(Z, t, t + 1);
+        const uint32_t tn = x.y;
+        if (tn >= t_end) break;
+        t = tn;
+        rec = rec_at(t);
+        if constexpr (kCount) ++n_visits;
+      }
+    };
+
+    // The walk is a depth-first search over the implicit prefix tree of the
+    // item's sorted texts.  Level D holds the state after D residues shared by
+    // every text of [t, g_end) and iterates the level's sibling groups (texts
+    // sharing D+1 residues; the group of t ends at nxt[D]): one text step on
+    // the group's residue D; when no lane is within k the whole group is
+    // skipped, otherwise the walk descends into it (or, with D+1 = n, the
+    // group is a run of identical texts that all take the lanes' edges).
+    auto level = [&](auto self, auto depth_tag, uint32_t pVP, uint32_t pVN, uint32_t pZ, uint32_t t,
+                     uint32_t g_end) __attribute__((always_inline)) -> void {
+      constexpr int D = decltype(depth_tag)::value;
+      const uint32_t mj = m_item << D;  // the diagonal row of step D
+      // of a group's first text only the code word of residue D and the
+      // group end are read
+      struct Part {
+        uint32_t w[D / 6 + 1];
+        uint32_t nxt[D + 1];
+      };
+      auto part_at = [&](uint32_t u) {
+        Part q;
+        const uint32_t off = (u - tb0) * (uint32_t)sizeof(SeqRec);
+        q.w[D / 6] = load_const_at<uint32_t>(tbase, off + 4u * (D / 6));
+        q.nxt[D] = load_const_at<uint32_t>(tbase, off + (uint32_t)offsetof(SeqRec, nxt) + 4u * D);
+        return q;
+      };
+      Part rec = part_at(t);  // the first group's text (the parent's current one)
+      for (;;) {
+        const uint32_t tn = min(rec.nxt[D], g_end);  // end of t's group (nxt[D] > t)
+        uint32_t VP = pVP, VN = pVN, Z = pZ;
+        bool alive;
+        TCR_STEP(rec, D, mj)
+        if (alive) {
+          if (D + 1 == (int)n) {
+            emit(Z, t, tn);
+          } else if constexpr (D + 1 < kLoopDepth) {
+            self(self, Tag<D + 1>{}, VP, VN, Z, t, tn);
+          } else {
+            leaf(VP, VN, Z, t, tn);
+          }
+        }
+        if (tn >= g_end) break;
+        t = tn;
+        rec = part_at(t);
+        if constexpr (kCount) ++n_visits;
+      }
+    };
+
+    uint32_t t = tb;
+    if (d.tri) {
+      // the ragged texts of a triangle item: patterns at or after the text
+      // are masked, so neither jumps nor shared state apply
+      const uint32_t rend = min(te, tri_end);
+      for (; t < rend; ++t) {
+        const SeqRec rec = rec_at(t);
+        if constexpr (kCount) ++n_visits;
+        const uint32_t dt = t - gbase;
+        uint32_t Z = z_item;
+        if constexpr (kPack == 2) {
+          if (lane >= dt) Z |= 0xFFFFu;
+          if (lane + kWave >= dt) Z |= 0xFFFF0000u;
+        } else {
+          if (lane >= dt) Z = ~0u;
+        }
+        const uint2 x = chain(Tag<0>{}, Tag<true>{}, rec, t, Mm, 0u, Z);
+        if (x.x == 32) emit(Z, t, t + 1);
+      }
+    }
+    if (t < te) {
+      if constexpr (kCount) ++n_visits;
+      level(level, Tag<0>{}, Mm, 0u, z_item, t, te);
+    }
+    if (kPeqLds) __builtin_amdgcn_wave_barrier();
+#undef TCR_STEP
 #undef TCR_EQ
 #undef TCR_CODE
-    }
-    };
-    if (d.tri) walk(Tag<1>{}, min(te, tri_end));
-    walk(Tag<0>{}, te);
-    if (kPeqLds) __builtin_amdgcn_wave_barrier();
   };
 
   // a wave starts on its own queue stripe and moves on when it runs dry; it
@@ -501,6 +502,13 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     else run_item(Tag<1>{}, d, g, c);
   }
   if (staged) flush();
+  if constexpr (kCount) {
+    if (lane == 0) {
+      atomicAdd(&cnt->visits, (unsigned long long)n_visits);
+      atomicAdd(&cnt->steps, (unsigned long long)n_steps);
+      atomicAdd(&cnt->steps_packed, (unsigned long long)n_steps_packed);
+    }
+  }
 }
 
 }  // namespace
@@ -514,18 +522,23 @@ uint32_t pair_grid_blocks(int device, uint32_t waves_per_simd) {
 }
 
 void launch_pairs(const PairArgs& a, uint32_t grid_blocks, bool peq_lds, hipStream_t st) {
-#define TCR_LAUNCH(LDS, MODE)                                                                              \
-  hipLaunchKernelGGL((k_pairs<LDS, MODE>), dim3(grid_blocks), dim3(kBlock), 0, st, a.descs, a.item_base, a.plan, \
-                     a.cnt, a.edges, a.edist, a.capacity, a.k)
+#define TCR_LAUNCH(LDS, MODE, COUNT)                                                                      \
+  hipLaunchKernelGGL((k_pairs<LDS, MODE, COUNT>), dim3(grid_blocks), dim3(kBlock), 0, st, a.descs, a.item_base, \
+                     a.plan, a.cnt, a.edges, a.edist, a.capacity, a.k)
   const int mode = a.k == 1 ? 1 : (a.k == 2 ? 2 : 0);
-  if (peq_lds) {
-    if (mode == 1) TCR_LAUNCH(true, 1);
-    else if (mode == 2) TCR_LAUNCH(true, 2);
-    else TCR_LAUNCH(true, 0);
+  if (a.count_work) {
+    // the counting variant walks exactly as the others; one mask location
+    if (mode == 1) TCR_LAUNCH(false, 1, true);
+    else if (mode == 2) TCR_LAUNCH(false, 2, true);
+    else TCR_LAUNCH(false, 0, true);
+  } else if (peq_lds) {
+    if (mode == 1) TCR_LAUNCH(true, 1, false);
+    else if (mode == 2) TCR_LAUNCH(true, 2, false);
+    else TCR_LAUNCH(true, 0, false);
   } else {
-    if (mode == 1) TCR_LAUNCH(false, 1);
-    else if (mode == 2) TCR_LAUNCH(false, 2);
-    else TCR_LAUNCH(false, 0);
+    if (mode == 1) TCR_LAUNCH(false, 1, false);
+    else if (mode == 2) TCR_LAUNCH(false, 2, false);
+    else TCR_LAUNCH(false, 0, false);
   }
 #undef TCR_LAUNCH
 }

@@ -181,6 +181,7 @@ void stage_pairs(Pipeline& pl, const PlanPart* d_parts, uint32_t n_parts, const 
   a.capacity = capacity;
   a.texts_per_item = sched.texts_per_item;
   a.k = k;
+  a.count_work = sched.count_work;
   if (ev0) (void)hipEventRecord(ev0, st);
   launch_pairs(a, grid_blocks, sched.peq_lds, st);
   if (ev1) (void)hipEventRecord(ev1, st);

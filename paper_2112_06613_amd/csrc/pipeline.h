@@ -71,6 +71,7 @@ struct Sched {
   bool peq_lds = false;
   bool pack = true;  // two patterns per lane for patterns of <= 16 residues
   bool tuned = false;  // chosen by the autotuner
+  bool count_work = false;  // pair kernel's counting variant (same traversal)
 };
 
 // Device buffers of one build pipeline (encode -> sort -> bucket -> plan ->

@@ -54,12 +54,16 @@ __global__ void k_reset_counters(Counters* c) {
     c->edges = 0;
     c->err = kNoError;
     c->fault = 0;
+    c->visits = c->steps = c->steps_packed = 0;
   }
 }
 
 __global__ void k_reset_work(Counters* c) {
   if (threadIdx.x < kQueueStripes) c->queue[threadIdx.x].next = 0;
-  if (threadIdx.x == 0) c->edges = 0;
+  if (threadIdx.x == 0) {
+    c->edges = 0;
+    c->visits = c->steps = c->steps_packed = 0;
+  }
 }
 
 __global__ void k_record_keys(const SeqRec* __restrict__ rec, uint32_t n, int nres, int len_shift,
