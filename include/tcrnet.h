@@ -96,12 +96,12 @@ typedef struct {
 } tcrnet_opts;
 
 #define TCRNET_F_NO_AUTOTUNE 1u   /* never consult or run the autotuner */
-#define TCRNET_F_PEQ_LDS 2u       /* keep pattern bit masks in LDS (default for
-                                     builds of at least 2^18 sequences) */
+#define TCRNET_F_PEQ_LDS 2u       /* keep pattern bit masks in LDS (default: in
+                                     VGPRs) */
 #define TCRNET_F_NO_PACK 4u       /* one pattern per lane also for patterns of <= 16
                                      residues (default: two, in 16-bit halves) */
-#define TCRNET_F_PEQ_VGPR 8u      /* keep pattern bit masks in VGPRs (default for
-                                     smaller builds and for serving) */
+#define TCRNET_F_PEQ_VGPR 8u      /* keep pattern bit masks in VGPRs (the
+                                     default) */
 #define TCRNET_F_COUNT_WORK 16u   /* run the pair kernel's counting variant: the
                                      same walk, also counting visited texts and
                                      wave text steps (tcrnet_build_info); slower,
@@ -220,7 +220,7 @@ TCRNET_API void tcrnet_graph_free(tcrnet_graph* g);
  * Time candidate pair-kernel schedules and keep the fastest in the context
  * for later launches of the same form, size class (bits of the sequence
  * count) and k.  Candidates: texts per work item 512 .. 16384 (powers of
- * two) x resident waves per SIMD {4, 8} x pattern masks in VGPRs or LDS x
+ * two) x resident waves per SIMD {4, 6, 8} x pattern masks in VGPRs or LDS x
  * two patterns per lane on or off (off only, with TCRNET_F_NO_PACK).  Each
  * candidate is timed as the device time of its whole launch sequence, the
  * fastest of two runs.  Results are exact for every candidate (the calls

@@ -63,15 +63,15 @@ namespace tcr {
 
 Sched pick_sched(const tcrnet_ctx* ctx, uint64_t n, int k, int form) {
   Sched s;
-  // Pattern masks in LDS leave the pair kernel 79 VGPRs (six waves per SIMD
-  // instead of five): faster once a launch keeps the chip full for most of
-  // its time (N = 800,000: 2.61 -> 2.50 ms at k = 1, 25.1 -> 23.4 ms at
-  // k = 2; N = 300,000: 5.75 -> 5.41 ms at k = 2); below that the tail of
-  // partly filled SIMDs favours the masks in VGPRs, whose reads are off the
-  // LDS latency.  Work items shrink with the launch (default_texts_per_item):
-  // its tail is then shorter (N = 50,000, k = 2: 1.78 ms at 16,384 texts per
-  // item, 0.49 ms at 512).
-  s.peq_lds = n >= kPeqLdsMinSeqs;
+  // Pattern masks in VGPRs: the sibling loops then wait on no LDS read and
+  // the walk-record prefetch is the only scalar-memory traffic in flight
+  // (N = 800,000, k = 1: 1.59 ms against 1.66 with the masks in LDS; 50,000:
+  // 0.207 against 0.220 ms).  The walk's registers allow six waves per SIMD,
+  // so a persistent grid of six blocks per CU.  Work items shrink with the
+  // launch (default_texts_per_item): its tail is then shorter (N = 50,000,
+  // k = 2: 1.78 ms at 16,384 texts per item, 0.49 ms at 512).
+  s.peq_lds = false;
+  s.waves_per_simd = kPairWavesPerSimd;
   s.texts_per_item = default_texts_per_item(n);
   if (!(ctx->opts.flags & TCRNET_F_NO_AUTOTUNE)) {
     TuneKey key;

@@ -37,6 +37,26 @@ struct alignas(64) SeqRec {
 
 static_assert(sizeof(SeqRec) == 64, "one record = one 64-byte line");
 
+// What the pair kernel's prefix-tree walk reads of a text at its first
+// kWalkDepth residues (16 bytes, four to a 64-byte scalar-cache line).
+//   w0:     residue codes 0..5 (as SeqRec::w[0])
+//   nxt[d]: the end of the text's depth-(d+1) prefix group as an offset from
+//           the text's own sorted position, capped at 65535 (a capped group
+//           is walked as several groups of the same residues: same result)
+constexpr int kWalkDepth = 6;
+struct alignas(16) WalkRec {
+  uint32_t w0;
+  uint16_t nxt[kWalkDepth];
+};
+static_assert(sizeof(WalkRec) == 16, "four walk records to a 64-byte line");
+
+// A sorted sequence set's record buffer holds its n SeqRec followed by their n
+// WalkRec (same order).
+__host__ __device__ inline const WalkRec* walk_of(const SeqRec* srec, uint32_t n) {
+  return reinterpret_cast<const WalkRec*>(srec + n);
+}
+constexpr uint64_t kSortedRecBytes = sizeof(SeqRec) + sizeof(WalkRec);  // per sequence
+
 // Bit masks of one pattern: eq[c] has bit q set iff residue q has code c
 // (Myers' Peq table).  80 bytes.
 struct PeqRec {
@@ -53,6 +73,7 @@ struct alignas(16) Desc {
   const SeqRec* prec;    // pattern-side records (lane side)
   const PeqRec* ppeq;    // pattern-side bit masks
   const SeqRec* trec;    // text-side records (wave-uniform side)
+  const WalkRec* twalk;  // text-side walk records
   uint32_t p0, np;       // pattern range (sorted positions in prec)
   uint32_t t0, nt;       // text range (sorted positions in trec)
   uint32_t m, n;         // lengths

@@ -151,7 +151,7 @@ struct Tag {
 // that are still alive after kLoopDepth residues run the rest of their steps
 // one text at a time.  Must not exceed kSkipDepths (the group ends a record
 // holds).
-constexpr int kLoopDepth = 6;
+constexpr int kLoopDepth = kWalkDepth;
 static_assert(kLoopDepth <= kSkipDepths, "a sibling loop needs the group end of its depth");
 
 // Byte offset of the id field in a SeqRec.
@@ -297,9 +297,10 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
 // (mj) into Z; alive: some lane still within k.
 #define TCR_EQ(cc) (kPeqLds ? wave_eq[(cc) * kWave + lane] : eq[(cc)])
 #define TCR_CODE(rr, q) (((rr).w[(q) / 6] >> (5 * ((q) % 6))) & 31u)
-#define TCR_STEP(rr, J, mj)                                                    \
+#define TCR_STEP(rr, J, mj) TCR_STEP_CODE(TCR_CODE(rr, J), mj)
+#define TCR_STEP_CODE(code, mj)                                                \
   {                                                                            \
-    const uint32_t Eq = TCR_EQ(TCR_CODE(rr, J));                               \
+    const uint32_t Eq = TCR_EQ(code);                                          \
     uint32_t D0;                                                               \
     if constexpr (kPack == 2) {                                                \
       D0 = (pk_add(Eq & VP, VP) ^ VP) | Eq | VN;                               \
@@ -399,28 +400,31 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     auto level = [&](auto self, auto depth_tag, uint32_t pVP, uint32_t pVN, uint32_t pZ, uint32_t t,
                      uint32_t g_end) __attribute__((always_inline)) -> void {
       constexpr int D = decltype(depth_tag)::value;
-      const uint32_t mj = m_item << D;  // the diagonal row of step D
-      // of a group's first text only the code word of residue D and the
-      // group end are read
-      struct Part {
-        uint32_t w[D / 6 + 1];
-        uint32_t nxt[D + 1];
-      };
-      auto part_at = [&](uint32_t u) {
-        Part q;
-        const uint32_t off = (u - tb0) * (uint32_t)sizeof(SeqRec);
-        q.w[D / 6] = load_const_at<uint32_t>(tbase, off + 4u * (D / 6));
-        q.nxt[D] = load_const_at<uint32_t>(tbase, off + (uint32_t)offsetof(SeqRec, nxt) + 4u * D);
-        return q;
-      };
-      Part rec = part_at(t);  // the first group's text (the parent's current one)
+      // the diagonal row of step D, kept in a VGPR (scalar registers are the
+      // scarce ones across the nested loops)
+      uint32_t mj = m_item << D;
+      asm volatile("" : "+v"(mj));
+      // a group's first text is read from its 16-byte walk record (the code
+      // word of residues 0..5 and the group ends): one scalar load of the
+      // whole record (the 16-bit fields are taken out of their dwords)
+      auto part_at = [&](uint32_t u) { return load_const_at<uint4>(d.twalk, u * (uint32_t)sizeof(WalkRec)); };
+      uint4 rec = part_at(t);  // the first group's text (the parent's current one)
       for (;;) {
-        const uint32_t tn = min(rec.nxt[D], g_end);  // end of t's group (nxt[D] > t)
+        const uint32_t nw = D / 2 == 0 ? rec.y : (D / 2 == 1 ? rec.z : rec.w);
+        const uint32_t nrel = D % 2 == 0 ? (nw & 0xFFFFu) : (nw >> 16);
+        const uint32_t tn = min(t + nrel, g_end);  // end of t's group (nrel >= 1)
+        // the next group's record is requested now (clamped into the range,
+        // read-only), so that its latency overlaps this group's step
+        const uint4 nrec = part_at(min(tn, g_end - 1u));
         uint32_t VP = pVP, VN = pVN, Z = pZ;
         bool alive;
-        TCR_STEP(rec, D, mj)
+        TCR_STEP_CODE((rec.x >> (5 * D)) & 31u, mj)
         if (alive) {
-          if (D + 1 == (int)n) {
+          // a per-iteration copy of n the compiler cannot see through: the
+          // test is one compare here instead of a mask held per level
+          uint32_t nn = n;
+          asm volatile("" : "+s"(nn));
+          if (nn == (uint32_t)D + 1u) {
             emit(Z, t, tn);
           } else if constexpr (D + 1 < kLoopDepth) {
             self(self, Tag<D + 1>{}, VP, VN, Z, t, tn);
@@ -430,7 +434,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
         }
         if (tn >= g_end) break;
         t = tn;
-        rec = part_at(t);
+        rec = nrec;
         if constexpr (kCount) ++n_visits;
       }
     };
@@ -461,6 +465,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     }
     if (kPeqLds) __builtin_amdgcn_wave_barrier();
 #undef TCR_STEP
+#undef TCR_STEP_CODE
 #undef TCR_EQ
 #undef TCR_CODE
   };

@@ -51,8 +51,8 @@ struct DevBuf {
   T* as() const { return static_cast<T*>(p); }
 };
 
-// Builds over at least this many sequences keep pattern masks in LDS.
-constexpr uint64_t kPeqLdsMinSeqs = 1ull << 18;
+// Resident waves per SIMD of the pair kernel (its register count allows six).
+constexpr uint32_t kPairWavesPerSimd = 6;
 
 // Default texts per work item for a launch over n sequences: about n / 195,
 // rounded down to a power of two in [512, 16384] (measured best at 50,000 to
@@ -67,7 +67,7 @@ inline uint32_t default_texts_per_item(uint64_t n) {
 // Pair-kernel schedule.
 struct Sched {
   uint32_t texts_per_item = 16384;
-  uint32_t waves_per_simd = 8;
+  uint32_t waves_per_simd = kPairWavesPerSimd;
   bool peq_lds = false;
   bool pack = true;  // two patterns per lane for patterns of <= 16 residues
   bool tuned = false;  // chosen by the autotuner

@@ -90,14 +90,14 @@ def test_medium_k2_sampled_rows_and_soundness(tn, ctx, orc):
 def test_paper_scale_k1_bit_exact(tn, ctx, orc):
     s = synth.paper_scale()
     g = tn.tcrnet_build(ctx, s, 1)
-    info = ctx.last_info()  # the defaults at this size: masks in LDS, 4,096 texts per item
-    assert info["peq_lds"] == 1 and info["texts_per_item"] == 4096
+    info = ctx.last_info()  # the defaults at this size: masks in VGPRs, 4,096 texts per item
+    assert info["peq_lds"] == 0 and info["texts_per_item"] == 4096
     e, d = orc.k1_build(s)
     _eq(g, e, d)
-    # the same launch with the pattern masks in VGPRs
-    with tn.Context(0, flags=tn.TCRNET_F_PEQ_VGPR) as c:
+    # the same launch with the pattern masks in LDS
+    with tn.Context(0, flags=tn.TCRNET_F_PEQ_LDS) as c:
         gv = tn.tcrnet_build(c, s, 1)
-        assert c.last_info()["peq_lds"] == 0
+        assert c.last_info()["peq_lds"] == 1
     _eq(gv, e, d)
     # DP oracle on sampled rows (full rows of 800,000 comparisons each)
     rng = np.random.default_rng(11)
