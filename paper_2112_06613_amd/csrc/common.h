@@ -38,24 +38,26 @@ struct alignas(64) SeqRec {
 static_assert(sizeof(SeqRec) == 64, "one record = one 64-byte line");
 
 // What the pair kernel's prefix-tree walk reads of a text at its first
-// kWalkDepth residues (16 bytes, four to a 64-byte scalar-cache line).
-//   w0:     residue codes 0..5 (as SeqRec::w[0])
-//   nxt[d]: the end of the text's depth-(d+1) prefix group as an offset from
-//           the text's own sorted position, capped at 65535 (a capped group
-//           is walked as several groups of the same residues: same result)
+// kWalkDepth residues: one dense array per depth d (8 bytes a text, eight to
+// a 64-byte scalar-cache line), entry s = {8 * (end of s's depth-(d+1)
+// prefix group), code of residue d}; the group end is a byte offset into the
+// same array, so the walk moves through it with no index arithmetic.  Each
+// array has one more entry than the set (a valid read one past the end).
 constexpr int kWalkDepth = 6;
-struct alignas(16) WalkRec {
-  uint32_t w0;
-  uint16_t nxt[kWalkDepth];
+struct WalkEnt {
+  uint32_t end8;  // 8 * group end (a sorted position <= n)
+  uint32_t code;  // residue d of the text (0..19)
 };
-static_assert(sizeof(WalkRec) == 16, "four walk records to a 64-byte line");
+static_assert(sizeof(WalkEnt) == 8, "eight walk entries to a 64-byte line");
 
-// A sorted sequence set's record buffer holds its n SeqRec followed by their n
-// WalkRec (same order).
-__host__ __device__ inline const WalkRec* walk_of(const SeqRec* srec, uint32_t n) {
-  return reinterpret_cast<const WalkRec*>(srec + n);
+// A sorted sequence set's record buffer holds its n SeqRec, then the
+// kWalkDepth walk arrays of n + 1 entries each.
+__host__ __device__ inline const WalkEnt* walk_of(const SeqRec* srec, uint32_t n) {
+  return reinterpret_cast<const WalkEnt*>(srec + n);
 }
-constexpr uint64_t kSortedRecBytes = sizeof(SeqRec) + sizeof(WalkRec);  // per sequence
+__host__ __device__ inline uint64_t sorted_rec_bytes(uint64_t n) {
+  return n * sizeof(SeqRec) + (uint64_t)kWalkDepth * (n + 1) * sizeof(WalkEnt);
+}
 
 // Bit masks of one pattern: eq[c] has bit q set iff residue q has code c
 // (Myers' Peq table).  80 bytes.
@@ -73,7 +75,8 @@ struct alignas(16) Desc {
   const SeqRec* prec;    // pattern-side records (lane side)
   const PeqRec* ppeq;    // pattern-side bit masks
   const SeqRec* trec;    // text-side records (wave-uniform side)
-  const WalkRec* twalk;  // text-side walk records
+  const WalkEnt* twalk;  // text-side walk arrays (depth 0; depth d at + d * tw_len)
+  uint32_t tw_len;       // entries of one walk array (text set size + 1)
   uint32_t p0, np;       // pattern range (sorted positions in prec)
   uint32_t t0, nt;       // text range (sorted positions in trec)
   uint32_t m, n;         // lengths

@@ -397,44 +397,44 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     // the group's residue D; when no lane is within k the whole group is
     // skipped, otherwise the walk descends into it (or, with D+1 = n, the
     // group is a run of identical texts that all take the lanes' edges).
-    auto level = [&](auto self, auto depth_tag, uint32_t pVP, uint32_t pVN, uint32_t pZ, uint32_t t,
-                     uint32_t g_end) __attribute__((always_inline)) -> void {
+    //
+    // Positions here are byte offsets into the walk arrays (8 * sorted
+    // position): t8 is the group's first text, g_end8 the end of the range.
+    auto level = [&](auto self, auto depth_tag, uint32_t pVP, uint32_t pVN, uint32_t pZ, uint32_t t8,
+                     uint32_t g_end8) __attribute__((always_inline)) -> void {
       constexpr int D = decltype(depth_tag)::value;
       // the diagonal row of step D, kept in a VGPR (scalar registers are the
       // scarce ones across the nested loops)
       uint32_t mj = m_item << D;
       asm volatile("" : "+v"(mj));
-      // a group's first text is read from its 16-byte walk record (the code
-      // word of residues 0..5 and the group ends): one scalar load of the
-      // whole record (the 16-bit fields are taken out of their dwords)
-      auto part_at = [&](uint32_t u) { return load_const_at<uint4>(d.twalk, u * (uint32_t)sizeof(WalkRec)); };
-      uint4 rec = part_at(t);  // the first group's text (the parent's current one)
+      const WalkEnt* walk = d.twalk + (uint64_t)D * d.tw_len;  // this depth's walk array
+      auto ent_at = [&](uint32_t u8) { return load_const_at<uint2>(walk, u8); };
+      uint2 rec = ent_at(t8);  // the first group's text (the parent's current one)
       for (;;) {
-        const uint32_t nw = D / 2 == 0 ? rec.y : (D / 2 == 1 ? rec.z : rec.w);
-        const uint32_t nrel = D % 2 == 0 ? (nw & 0xFFFFu) : (nw >> 16);
-        const uint32_t tn = min(t + nrel, g_end);  // end of t's group (nrel >= 1)
-        // the next group's record is requested now (clamped into the range,
-        // read-only), so that its latency overlaps this group's step
-        const uint4 nrec = part_at(min(tn, g_end - 1u));
+        const uint32_t code = rec.y;
+        const uint32_t tn8 = min(rec.x, g_end8);  // end of t's group (> t)
+        // the next group's entry is requested now (the array has an entry
+        // at the end of every range), so that its latency overlaps this
+        // group's step
+        rec = ent_at(tn8);
         uint32_t VP = pVP, VN = pVN, Z = pZ;
         bool alive;
-        TCR_STEP_CODE((rec.x >> (5 * D)) & 31u, mj)
+        TCR_STEP_CODE(code, mj)
         if (alive) {
           // a per-iteration copy of n the compiler cannot see through: the
           // test is one compare here instead of a mask held per level
           uint32_t nn = n;
           asm volatile("" : "+s"(nn));
           if (nn == (uint32_t)D + 1u) {
-            emit(Z, t, tn);
+            emit(Z, t8 >> 3, tn8 >> 3);
           } else if constexpr (D + 1 < kLoopDepth) {
-            self(self, Tag<D + 1>{}, VP, VN, Z, t, tn);
+            self(self, Tag<D + 1>{}, VP, VN, Z, t8, tn8);
           } else {
-            leaf(VP, VN, Z, t, tn);
+            leaf(VP, VN, Z, t8 >> 3, tn8 >> 3);
           }
         }
-        if (tn >= g_end) break;
-        t = tn;
-        rec = nrec;
+        if (tn8 >= g_end8) break;
+        t8 = tn8;
         if constexpr (kCount) ++n_visits;
       }
     };
@@ -461,7 +461,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     }
     if (t < te) {
       if constexpr (kCount) ++n_visits;
-      level(level, Tag<0>{}, Mm, 0u, z_item, t, te);
+      level(level, Tag<0>{}, Mm, 0u, z_item, 8u * t, 8u * te);
     }
     if (kPeqLds) __builtin_amdgcn_wave_barrier();
 #undef TCR_STEP

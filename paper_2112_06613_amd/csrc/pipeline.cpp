@@ -91,7 +91,7 @@ void pipeline_sizes(uint64_t n, uint32_t n_seg, int k, uint32_t T, uint64_t capa
       nn * 8,                                       // key2
       nn * 4,                                       // val
       nn * 4,                                       // val2
-      nn * kSortedRecBytes,                         // srec (records, then walk records)
+      sorted_rec_bytes(nn),                         // srec (records, then walk arrays)
       nn * sizeof(PeqRec),                          // speq
       ((uint64_t)n_seg * 64 + 1) * 4,               // off
       (uint64_t)max_desc * sizeof(Desc),            // descs

@@ -210,14 +210,15 @@ __global__ void k_gather(const SeqRec* __restrict__ rec, const uint32_t* __restr
   r.len = packed;
   srec[s] = r;
   {
-    WalkRec wr;
-    wr.w0 = r.w[0];
+    WalkEnt* walk = const_cast<WalkEnt*>(walk_of(srec, (uint32_t)n));
 #pragma unroll
     for (int d = 0; d < kWalkDepth; ++d) {
-      const uint64_t rel = r.nxt[d] - s;
-      wr.nxt[d] = (uint16_t)(rel < 65535u ? rel : 65535u);
+      WalkEnt e;
+      e.end8 = 8u * r.nxt[d];
+      e.code = (r.w[0] >> (5 * d)) & 31u;
+      walk[(uint64_t)d * (n + 1) + s] = e;
+      if (s + 1 == n) walk[(uint64_t)d * (n + 1) + n] = WalkEnt{8u * (uint32_t)n, 0u};  // the extra entry
     }
-    const_cast<WalkRec*>(walk_of(srec, (uint32_t)n))[s] = wr;
   }
   // bit planes of the residue codes, then Peq[c] = positions whose code is c
   uint32_t pl[5] = {0, 0, 0, 0, 0};
@@ -257,7 +258,8 @@ struct Entry {
   const SeqRec* prec;
   const PeqRec* ppeq;
   const SeqRec* trec;
-  const WalkRec* twalk;
+  const WalkEnt* twalk;
+  uint32_t tw_len;
   uint32_t p0, np, t0, nt, m, n, tri, ndesc, pack;
   uint64_t items, pairs;
 };
@@ -281,7 +283,8 @@ __device__ Entry entry_shape(const PlanPart& part, uint32_t e, int k, uint32_t T
   r.prec = part.a.srec;
   r.ppeq = part.a.speq;
   r.trec = part.a.srec;
-  r.twalk = walk_of(part.a.srec, part.a.off[part.a.n_seg * 64]);
+  r.tw_len = part.a.off[part.a.n_seg * 64] + 1;
+  r.twalk = walk_of(part.a.srec, r.tw_len - 1);
   if (!part.cross) {
     const uint32_t per_seg = 32u * (uint32_t)(k + 1);
     const uint32_t seg = e / per_seg;
@@ -333,13 +336,15 @@ __device__ Entry entry_shape(const PlanPart& part, uint32_t e, int k, uint32_t T
       r.p0 = part.a.off[La]; r.np = na;
       r.t0 = part.b.off[Lb]; r.nt = nb;
       r.prec = part.a.srec; r.ppeq = part.a.speq; r.trec = part.b.srec;
-      r.twalk = walk_of(part.b.srec, part.b.off[part.b.n_seg * 64]);
+      r.tw_len = part.b.off[part.b.n_seg * 64] + 1;
+      r.twalk = walk_of(part.b.srec, r.tw_len - 1);
     } else {
       r.m = (uint32_t)Lb; r.n = La;
       r.p0 = part.b.off[Lb]; r.np = nb;
       r.t0 = part.a.off[La]; r.nt = na;
       r.prec = part.b.srec; r.ppeq = part.b.speq; r.trec = part.a.srec;
-      r.twalk = walk_of(part.a.srec, part.a.off[part.a.n_seg * 64]);
+      r.tw_len = part.a.off[part.a.n_seg * 64] + 1;
+      r.twalk = walk_of(part.a.srec, r.tw_len - 1);
     }
     r.ndesc = 1;
     r.pack = pack_for(r.m, k, pack_ok);
@@ -463,6 +468,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(const PlanPart* __restric
           d.ppeq = en.ppeq;
           d.trec = en.trec;
           d.twalk = en.twalk;
+          d.tw_len = en.tw_len;
           d.m = en.m;
           d.n = en.n;
           d.tri = en.tri;

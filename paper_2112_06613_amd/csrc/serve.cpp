@@ -56,7 +56,7 @@ struct Segment {
   hipError_t alloc(uint32_t count) {
     n = count;
     hipError_t e;
-    if ((e = srec.ensure((uint64_t)(count ? count : 1) * kSortedRecBytes)) != hipSuccess) return e;
+    if ((e = srec.ensure(sorted_rec_bytes(count ? count : 1))) != hipSuccess) return e;
     if ((e = speq.ensure((uint64_t)(count ? count : 1) * sizeof(PeqRec))) != hipSuccess) return e;
     return off.ensure(65 * 4);
   }
@@ -193,7 +193,8 @@ int32_t check_request_seqs(const tcrnet_seqs* s) {
 }
 
 uint64_t request_bytes(uint32_t m, uint64_t capacity, uint32_t n_parts) {
-  return (uint64_t)m * (sizeof(SeqRec) + kSortedRecBytes + sizeof(PeqRec) + 40 + 64) + capacity * 40 +
+  return (uint64_t)m * sizeof(SeqRec) + sorted_rec_bytes(m) + (uint64_t)m * (sizeof(PeqRec) + 40 + 64) +
+         capacity * 40 +
          (uint64_t)n_parts * 160 * sizeof(Desc) + (1u << 16);
 }
 
@@ -635,8 +636,8 @@ int32_t tcrnet_index_create(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k_
     tcrnet_build_info info{};
     rc = run_pipeline(ctx, ctx->pipe, pp, ctx->stream, true, &ctx->out_pairs, &E, &info);
     if (rc) return rc;
-    // the sorted records and their walk records, which follow them
-    (void)hipMemcpyAsync(base->srec.p, ctx->pipe.srec.p, (uint64_t)n * kSortedRecBytes, hipMemcpyDeviceToDevice,
+    // the sorted records and their walk arrays, which follow them
+    (void)hipMemcpyAsync(base->srec.p, ctx->pipe.srec.p, sorted_rec_bytes(n), hipMemcpyDeviceToDevice,
                          ctx->stream);
     (void)hipMemcpyAsync(base->speq.p, ctx->pipe.speq.p, (uint64_t)n * sizeof(PeqRec), hipMemcpyDeviceToDevice,
                          ctx->stream);
