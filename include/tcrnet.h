@@ -91,7 +91,7 @@ typedef struct {
                                from N); too small only costs one re-run */
   uint64_t hbm_budget;      /* serving: bytes of device memory that admitted
                                requests may hold at once (0: 1/4 of free) */
-  uint32_t max_inflight;    /* serving: requests on the device at once (0: 4) */
+  uint32_t max_inflight;    /* serving: requests on the device at once (0: 8) */
   uint32_t flags;           /* TCRNET_F_* */
 } tcrnet_opts;
 
@@ -306,7 +306,14 @@ typedef struct {
   uint32_t snapshot_size; /* repertoire size the request saw */
   uint32_t is_insert;
   double latency_ms;      /* submit -> result ready on the host */
-  double device_ms;       /* first launch -> last kernel done */
+  double device_ms;       /* first launch -> last kernel done (HIP events on
+                             the request's stream: includes time its kernels
+                             waited for others to free the device) */
+  double queue_ms;        /* submit -> admission (waiting for a slot or
+                             device-memory budget, behind earlier requests) */
+  double admit_ms;        /* host work of the admission (staging, launches) */
+  uint32_t attempts;      /* pair-kernel launches (2 after an edge overflow) */
+  uint32_t parts;         /* planned parts (snapshot segments + own set) */
 } tcrnet_result_info;
 
 TCRNET_API int32_t tcrnet_result_pairs(const tcrnet_result* r, const uint32_t** pairs, uint64_t* n);

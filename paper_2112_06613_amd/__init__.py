@@ -61,7 +61,8 @@ class tcrnet_build_info(ctypes.Structure):
 
 class tcrnet_result_info(ctypes.Structure):
     _fields_ = [("seqno", ctypes.c_uint64), ("snapshot_size", ctypes.c_uint32), ("is_insert", ctypes.c_uint32),
-                ("latency_ms", ctypes.c_double), ("device_ms", ctypes.c_double)]
+                ("latency_ms", ctypes.c_double), ("device_ms", ctypes.c_double), ("queue_ms", ctypes.c_double),
+                ("admit_ms", ctypes.c_double), ("attempts", ctypes.c_uint32), ("parts", ctypes.c_uint32)]
 
 
 _P = ctypes.c_void_p

@@ -103,7 +103,9 @@ struct SetRef {
 // One part of a work plan.  self (cross == 0): all pairs inside each segment
 // of set a, lengths at most k apart.  cross: all pairs between set a (one
 // segment) and set b (one segment), lengths at most k apart; when the lengths
-// are equal, a supplies the patterns.
+// are equal, the set with fewer sequences of that length supplies the
+// patterns when it has at least 64 of them, else the other (a when the
+// counts are equal).
 struct PlanPart {
   SetRef a;
   SetRef b;

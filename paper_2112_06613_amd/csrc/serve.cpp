@@ -7,8 +7,11 @@
 // snapshot (the current segment list, shared ownership) and a sequence
 // number, and an insert appends its own segment for every later admission to
 // see.  When the list grows past kMaxDeltas extra segments, they are merged
-// (re-sorted on the device) into one new base for later admissions; older
-// snapshots keep their segments alive until their requests finish.
+// (re-sorted on the device, on a stream of its own): the insert segments
+// among themselves, or, once they reach an eighth of the base, everything
+// into a new base.  A merged segment replaces its inputs for later admissions
+// once its work has finished; older snapshots keep their segments alive until
+// their requests finish.
 //
 // Continuous batching.  kSlots-many requests are on the device at once, each
 // on its own stream (default priority) with its own pipeline buffers;
@@ -41,8 +44,14 @@ struct tcrnet_result {
 
 namespace {
 
-constexpr uint32_t kMaxDeltas = 8;       // insert segments before a merge
+constexpr uint32_t kMaxDeltas = 4;       // segments after the base before a merge
 constexpr uint32_t kDegHeadroom = 1u << 22;  // inserted nodes the degree array holds
+// Requests this large (and a threshold this high) find every buffer of their
+// slot already allocated: device and pinned-host frees synchronise the whole
+// device, so the serving loop must not grow buffers under load.
+constexpr uint32_t kReserveSeqs = 4096;
+constexpr int kReserveK = 2;
+constexpr uint32_t kDefaultSlots = 8;
 
 struct Segment {
   uint32_t n = 0;
@@ -71,6 +80,50 @@ struct Segment {
 };
 using SegPtr = std::shared_ptr<Segment>;
 
+// Segments no request or snapshot uses any more keep their device buffers
+// here for reuse: freeing them would synchronise the device mid-serving.  A
+// segment returns here when its last owner drops it, which happens only
+// after every request that read it has finished on the device (a request
+// failing with work in flight first waits for its stream).
+struct SegPool {
+  std::mutex mu;
+  std::vector<std::unique_ptr<Segment>> free;
+};
+using PoolPtr = std::shared_ptr<SegPool>;
+
+// A segment for `count` sequences: the smallest pooled one that holds them,
+// else a new one (sized with room to grow: merged bases grow with inserts).
+hipError_t take_segment(const PoolPtr& pool, uint32_t count, uint32_t headroom_pct, SegPtr* out) {
+  std::unique_ptr<Segment> got;
+  {
+    std::lock_guard<std::mutex> g(pool->mu);
+    const uint64_t need_rec = sorted_rec_bytes(count ? count : 1);
+    size_t best = pool->free.size();
+    for (size_t i = 0; i < pool->free.size(); ++i) {
+      const Segment& c = *pool->free[i];
+      if (c.srec.cap >= need_rec && c.speq.cap >= (uint64_t)(count ? count : 1) * sizeof(PeqRec) &&
+          (best == pool->free.size() || c.srec.cap < pool->free[best]->srec.cap))
+        best = i;
+    }
+    if (best < pool->free.size()) {
+      got = std::move(pool->free[best]);
+      pool->free.erase(pool->free.begin() + (long)best);
+    }
+  }
+  if (!got) got.reset(new Segment());
+  const uint32_t grow = count + (uint32_t)((uint64_t)count * headroom_pct / 100);
+  hipError_t e = got->alloc(grow);
+  if (e == hipSuccess) e = got->alloc(count);
+  memset(got->hcount, 0, sizeof got->hcount);
+  if (e != hipSuccess) return e;
+  PoolPtr keep = pool;
+  *out = SegPtr(got.release(), [keep](Segment* sp) {
+    std::lock_guard<std::mutex> g(keep->mu);
+    keep->free.emplace_back(sp);
+  });
+  return hipSuccess;
+}
+
 struct Request {
   uint64_t ticket = 0;
   std::vector<char> data;
@@ -79,7 +132,8 @@ struct Request {
   uint32_t hcount[33] = {0};  // length histogram of the batch (sizing only)
   int k = 1;
   bool insert = false;
-  Clock::time_point t_submit;
+  Clock::time_point t_submit, t_admit;
+  double admit_ms = 0.0;
   // admission
   uint64_t seqno = 0;
   std::vector<SegPtr> snap;
@@ -142,6 +196,7 @@ struct tcrnet_index {
   uint64_t n_promised = 0;  // resident sequences once every accepted insert is in (under mu)
   uint32_t deg_cap = 0;
   DevBuf deg;
+  PoolPtr pool = std::make_shared<SegPool>();  // declared before every SegPtr holder
   std::vector<SegPtr> segs;
   std::vector<std::unique_ptr<Slot>> slots;
   uint64_t budget = 0, used = 0;
@@ -151,7 +206,11 @@ struct tcrnet_index {
   hipStream_t merge_st = nullptr;
   Pipeline merge_pl;
   DevBuf merge_rec;
-  std::vector<std::pair<SegPtr, std::vector<SegPtr>>> retired;  // merged segment, inputs kept alive
+  // a merged segment still being built on merge_st: it replaces segs[merge_lo,
+  // merge_hi) once its work is done (until then admissions keep
+  // snapshotting the unmerged list)
+  SegPtr merging;
+  size_t merge_lo = 0, merge_hi = 0;
   // request queue (guarded by mu)
   std::mutex mu;
   std::condition_variable cv_work, cv_done;
@@ -242,6 +301,9 @@ void mark_failed_locked(tcrnet_index* idx, uint64_t seqno, const std::string& wh
 }
 
 void fail_request(tcrnet_index* idx, Slot* s, Request* r, int32_t status, const std::string& msg) {
+  // work already on the slot's stream may still read the snapshot's
+  // segments, which go back to the pool once the request lets go of them
+  if (s) (void)hipStreamSynchronize(s->st);
   if (r->insert && r->published) {
     std::lock_guard<std::mutex> g(idx->mu);
     mark_failed_locked(idx, r->seqno, "insert (admission " + std::to_string(r->seqno) + ") failed: " + msg);
@@ -288,9 +350,35 @@ hipError_t enqueue_pairs(tcrnet_index* idx, Slot* s) {
   return hipSuccess;
 }
 
+// Allocate a slot's buffers for requests of up to kReserveSeqs sequences at
+// k <= kReserveK against a fully fragmented snapshot.
+hipError_t reserve_slot(tcrnet_index* idx, Slot* s) {
+  hipError_t e;
+  const uint32_t m = kReserveSeqs;
+  const uint64_t cap = (uint64_t)m * 16;
+  const uint32_t n_parts = 2 * kMaxDeltas + 3;  // deltas keep coming while a merge is built
+  const uint32_t max_desc = (n_parts + 1) * plan_max_desc_cross(kReserveK) +
+                            plan_max_desc_self(1, kReserveK, idx->sched.texts_per_item, m);
+  if ((e = pipeline_reserve(s->pl, m, 1, kReserveK, idx->sched.texts_per_item, cap, max_desc)) != hipSuccess)
+    return e;
+  if ((e = s->d_pairs.ensure(cap * 8)) != hipSuccess || (e = s->d_counts.ensure((uint64_t)m * 4)) != hipSuccess ||
+      (e = s->d_data.ensure((uint64_t)m * TCRNET_MAX_LEN)) != hipSuccess ||
+      (e = s->d_off.ensure((uint64_t)(m + 1) * 8)) != hipSuccess ||
+      (e = s->d_parts.ensure((uint64_t)n_parts * sizeof(PlanPart))) != hipSuccess)
+    return e;
+  if ((e = s->h_data.ensure((uint64_t)m * TCRNET_MAX_LEN)) != hipSuccess ||
+      (e = s->h_off.ensure((uint64_t)(m + 1) * 8)) != hipSuccess ||
+      (e = s->h_parts.ensure((uint64_t)n_parts * sizeof(PlanPart))) != hipSuccess ||
+      (e = s->h_meta.ensure(sizeof(Meta))) != hipSuccess || (e = s->h_pairs.ensure(cap * 8 + 8)) != hipSuccess ||
+      (e = s->h_counts.ensure((uint64_t)m * 4 + 4)) != hipSuccess)
+    return e;
+  return hipSuccess;
+}
+
 // Admission of r onto slot s: snapshot, insert segment, stage 1, parts.
 hipError_t admit(tcrnet_index* idx, Slot* s, Request* r) {
   hipError_t e;
+  r->t_admit = Clock::now();
   r->seqno = idx->next_seqno++;
   r->snap = idx->segs;
   r->n_snap = idx->n_total;
@@ -299,7 +387,8 @@ hipError_t admit(tcrnet_index* idx, Slot* s, Request* r) {
   s->capacity = std::max<uint64_t>(4096, (uint64_t)r->m * 16);
   {
     // one item per wave (4 per block) in the first round; never more than
-    // the full persistent grid
+    // the full persistent grid (an uncapped grid of short-lived blocks was
+    // slower: 1.03 -> 1.26 ms for 4,096 queries at k = 2 against 800,000)
     const uint64_t want = (estimate_items(r, idx->sched.texts_per_item) + 3) / 4;
     s->grid = (uint32_t)std::min<uint64_t>(idx->grid, std::max<uint64_t>(16, want));
   }
@@ -326,8 +415,7 @@ hipError_t admit(tcrnet_index* idx, Slot* s, Request* r) {
       return e;
     SetOut out;
     if (r->insert) {
-      r->new_seg = std::make_shared<Segment>();
-      if ((e = r->new_seg->alloc(r->m)) != hipSuccess) return e;
+      if ((e = take_segment(idx->pool, r->m, 0, &r->new_seg)) != hipSuccess) return e;
       out.srec = r->new_seg->srec.as<SeqRec>();
       out.speq = r->new_seg->speq.as<PeqRec>();
       out.off = r->new_seg->off.as<uint32_t>();
@@ -377,25 +465,35 @@ hipError_t admit(tcrnet_index* idx, Slot* s, Request* r) {
   return enqueue_pairs(idx, s);
 }
 
-// Merge all current segments into one new base (on the merge stream).
+// Start merging segments on the merge stream, tiered: the insert segments
+// after the base are merged among themselves (a cost proportional to their
+// size) until together they reach an eighth of the base; then everything is
+// merged into a new base.  The result is published by publish_merge once its
+// work has finished, so no admission ever waits for a merge.
 hipError_t merge_segments(tcrnet_index* idx) {
   hipError_t e;
-  // the previous merge may still read the scratch buffers about to be reused
-  if ((e = hipStreamSynchronize(idx->merge_st)) != hipSuccess) return e;
-  const uint32_t n = idx->n_total;
-  auto merged = std::make_shared<Segment>();
-  if ((e = merged->alloc(n)) != hipSuccess) return e;
-  for (const SegPtr& seg : idx->segs)
-    for (int L = 0; L <= 32; ++L) merged->hcount[L] += seg->hcount[L];
+  uint64_t rest = 0;
+  for (size_t i = 1; i < idx->segs.size(); ++i) rest += idx->segs[i]->n;
+  const size_t lo = 8 * rest < (uint64_t)idx->segs[0]->n ? 1 : 0, hi = idx->segs.size();
+  uint32_t n = 0;
+  for (size_t i = lo; i < hi; ++i) n += idx->segs[i]->n;
+  SegPtr merged;
+  if ((e = take_segment(idx->pool, n, lo == 0 ? 25 : 100, &merged)) != hipSuccess) return e;
+  for (size_t i = lo; i < hi; ++i)
+    for (int L = 0; L <= 32; ++L) merged->hcount[L] += idx->segs[i]->hcount[L];
+  // (reserved with room for growth when the index was made)
   if ((e = idx->merge_rec.ensure((uint64_t)(n ? n : 1) * sizeof(SeqRec))) != hipSuccess) return e;
   if ((e = pipeline_reserve(idx->merge_pl, n, 1, 1, idx->sched.texts_per_item, 1, 1)) != hipSuccess) return e;
   uint64_t pos = 0;
-  for (const SegPtr& seg : idx->segs) {
+  for (size_t i = lo; i < hi; ++i) {
+    const SegPtr& seg = idx->segs[i];
     (void)hipStreamWaitEvent(idx->merge_st, seg->ready, 0);
     if (seg->n &&
         (e = hipMemcpyAsync(idx->merge_rec.as<SeqRec>() + pos, seg->srec.p, (uint64_t)seg->n * sizeof(SeqRec),
-                            hipMemcpyDeviceToDevice, idx->merge_st)) != hipSuccess)
+                            hipMemcpyDeviceToDevice, idx->merge_st)) != hipSuccess) {
+      (void)hipStreamSynchronize(idx->merge_st);  // before `merged` goes back to the pool
       return e;
+    }
     pos += seg->n;
   }
   SetOut out;
@@ -404,9 +502,23 @@ hipError_t merge_segments(tcrnet_index* idx) {
   out.off = merged->off.as<uint32_t>();
   stage_prepare_records(idx->merge_pl, idx->merge_rec.as<SeqRec>(), n, out, idx->merge_st);
   (void)hipEventRecord(merged->ready, idx->merge_st);
-  idx->retired.emplace_back(merged, idx->segs);
-  idx->segs.assign(1, merged);
+  idx->merging = merged;
+  idx->merge_lo = lo;
+  idx->merge_hi = hi;
   return hipSuccess;
+}
+
+// Publish a finished merge: the merged segment replaces the segments it
+// covers (snapshots of earlier admissions keep those alive); inserts
+// admitted while it was built stay behind it.
+void publish_merge(tcrnet_index* idx) {
+  if (!idx->merging || hipEventQuery(idx->merging->ready) != hipSuccess) return;
+  std::vector<SegPtr> segs(idx->segs.begin(), idx->segs.begin() + (long)idx->merge_lo);
+  segs.push_back(idx->merging);
+  segs.insert(segs.end(), idx->segs.begin() + (long)idx->merge_hi, idx->segs.end());
+  idx->segs.swap(segs);
+  idx->merging.reset();
+  idx->merge_lo = idx->merge_hi = 0;
 }
 
 // Checkpoint 1: counters are on the host.
@@ -483,6 +595,10 @@ void on_done(tcrnet_index* idx, Slot* s) {
   res->info.is_insert = r->insert ? 1 : 0;
   res->info.device_ms = dev_ms;
   res->info.latency_ms = std::chrono::duration<double, std::milli>(Clock::now() - r->t_submit).count();
+  res->info.queue_ms = std::chrono::duration<double, std::milli>(r->t_admit - r->t_submit).count();
+  res->info.admit_ms = r->admit_ms;
+  res->info.attempts = (uint32_t)s->attempts;
+  res->info.parts = s->n_parts;
   finish(idx, s, r);
 }
 
@@ -535,14 +651,11 @@ void worker_loop(tcrnet_index* idx) {
         idx->inflight++;
       }
       hipError_t e = admit(idx, free_slot, r);
+      r->admit_ms = std::chrono::duration<double, std::milli>(Clock::now() - r->t_admit).count();
       if (e != hipSuccess) fail_request(idx, free_slot, r, status_of(e), hipGetErrorString(e));
-      if (idx->segs.size() > 1 + kMaxDeltas) {
-        if ((e = merge_segments(idx)) != hipSuccess) {
-          std::lock_guard<std::mutex> g(idx->mu);
-          // later admissions would see a partly merged repertoire
-          mark_failed_locked(idx, idx->next_seqno, std::string("segment merge failed: ") + hipGetErrorString(e));
-        }
-      }
+      // a failed merge changes nothing (the unmerged list stays current);
+      // it is tried again after the next admission
+      if (idx->segs.size() > 1 + kMaxDeltas && !idx->merging) (void)merge_segments(idx);
       progressed = true;
     }
     // in-flight requests
@@ -560,18 +673,11 @@ void worker_loop(tcrnet_index* idx) {
         on_done(idx, s);
       }
     }
-    // merged segments whose inputs are no longer read
-    for (size_t i = 0; i < idx->retired.size();) {
-      if (hipEventQuery(idx->retired[i].first->ready) == hipSuccess) {
-        idx->retired.erase(idx->retired.begin() + (long)i);
-      } else {
-        ++i;
-      }
-    }
+    publish_merge(idx);
     if (progressed) continue;
     std::unique_lock<std::mutex> lk(idx->mu);
     if (idx->stop && idx->pending.empty() && idx->inflight == 0) break;
-    if (idx->inflight > 0 || !idx->retired.empty()) {
+    if (idx->inflight > 0 || idx->merging) {
       lk.unlock();
       std::this_thread::sleep_for(std::chrono::microseconds(20));
     } else {
@@ -614,8 +720,8 @@ int32_t tcrnet_index_create(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k_
   if ((e = idx->deg.ensure((uint64_t)idx->deg_cap * 4)) != hipSuccess) return hip_error(e, "degree array");
   launch_fill_u32(idx->deg.as<uint32_t>(), idx->deg_cap, 0u, ctx->stream);
   // base segment: the plain build at k_index gives the sorted set and degrees
-  auto base = std::make_shared<Segment>();
-  if ((e = base->alloc(n)) != hipSuccess) return hip_error(e, "segment allocation");
+  SegPtr base;
+  if ((e = take_segment(idx->pool, n, 0, &base)) != hipSuccess) return hip_error(e, "segment allocation");
   for (uint32_t i = 0; i < n; ++i) base->hcount[seqs->offsets[i + 1] - seqs->offsets[i]]++;
   if (n) {
     const uint64_t b0 = seqs->offsets[0], bytes = seqs->offsets[n] - b0;
@@ -654,11 +760,12 @@ int32_t tcrnet_index_create(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k_
   idx->sched = pick_sched(ctx, n, k_index);
   // requests are small next to the resident set: short work items keep many
   // waves busy on each request (measured best for 1-4,096 queries against
-  // 800,000 resident sequences)
-  if (!ctx->opts.texts_per_item) idx->sched.texts_per_item = 1024;
+  // 800,000 resident sequences: 3,425 queries at k = 2 in 0.854 ms at 512
+  // texts per item, 0.877 at 1,024, 1.02 at 2,048)
+  if (!ctx->opts.texts_per_item) idx->sched.texts_per_item = 512;
   // and such launches run mostly in their tail: pattern masks in VGPRs
   if (!(ctx->opts.flags & TCRNET_F_PEQ_LDS)) idx->sched.peq_lds = false;
-  const uint32_t n_slots = ctx->opts.max_inflight ? ctx->opts.max_inflight : 4;
+  const uint32_t n_slots = ctx->opts.max_inflight ? ctx->opts.max_inflight : kDefaultSlots;
   idx->grid = pair_grid_blocks(ctx->device, idx->sched.waves_per_simd);  // upper bound per request
   size_t free_b = 0, total_b = 0;
   (void)hipMemGetInfo(&free_b, &total_b);
@@ -670,7 +777,21 @@ int32_t tcrnet_index_create(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k_
     (void)hipEventCreateWithFlags(&s->ev_done, hipEventDisableTiming);
     (void)hipEventCreate(&s->ev_t0);
     (void)hipEventCreate(&s->ev_t1);
+    if ((e = reserve_slot(idx.get(), s.get())) != hipSuccess) return hip_error(e, "serving slot allocation");
     idx->slots.push_back(std::move(s));
+  }
+  // merge scratch for the repertoire with room for a quarter more inserts,
+  // and a spare segment of that size for the first full merge
+  {
+    SegPtr spare;
+    if ((e = take_segment(idx->pool, n + n / 4 + kReserveSeqs, 0, &spare)) != hipSuccess)
+      return hip_error(e, "merge workspace");
+  }
+  {
+    const uint64_t nm = (uint64_t)n + n / 4 + kReserveSeqs;
+    if ((e = idx->merge_rec.ensure(nm * sizeof(SeqRec))) != hipSuccess ||
+        (e = pipeline_reserve(idx->merge_pl, nm, 1, 1, idx->sched.texts_per_item, 1, 1)) != hipSuccess)
+      return hip_error(e, "merge workspace");
   }
   if ((e = hipStreamCreateWithFlags(&idx->merge_st, hipStreamNonBlocking)) != hipSuccess)
     return hip_error(e, "stream");

@@ -5,6 +5,8 @@ Snapshot rule checked here: a request sees the initial repertoire plus every
 insert admitted before it (lower sequence number).  Each result "in the mix"
 must equal the oracle's answer for that snapshot alone.
 """
+import time
+
 import numpy as np
 import pytest
 
@@ -112,11 +114,19 @@ def test_mixed_trace_snapshot_semantics(tn, ctx, orc):
         k = int(rng.integers(1, 3))
         ins = bool(rng.random() < 0.35)
         reqs.append((synth.queries(size, 600, 44, 1000 + i), k, ins))
+    q_last = synth.queries(20, 80000, synth.SEED_PAPER, 5999)
     with tn.tcrnet_index_create(ctx, base, 1) as idx:
         tickets = [tn.tcrnet_submit(idx, q, k, ins) for q, k, ins in reqs]
         results = [tn.tcrnet_wait(idx, t) for t in tickets]
         final_deg = idx.degree()
         final_n = idx.size()
+        # merges of the base and the insert segments are published once
+        # their device work is done: a later query reads a merged base and
+        # at most the 5 insert segments a merge waits for, not 1 + 10
+        # segments
+        time.sleep(0.2)
+        last = tn.tcrnet_query(idx, q_last, 2)
+        assert last.info["parts"] <= 6, last.info
     # replay in admission order against the oracle
     order = np.argsort([r.info["seqno"] for r in results])
     assert [results[i].info["seqno"] for i in order] == sorted(r.info["seqno"] for r in results)
@@ -212,11 +222,19 @@ def test_paper_scale_resident_mixed_trace(tn, ctx, orc):
         k = 1 if ins else int(rng.integers(1, 3))
         reqs.append((synth.queries(size, 80000, synth.SEED_PAPER, 5000 + i), k, ins))
     assert sum(r[2] for r in reqs) >= 9     # more than 8 insert segments: a merge runs
+    q_last = synth.queries(20, 80000, synth.SEED_PAPER, 5999)
     with tn.tcrnet_index_create(ctx, base, 1) as idx:
         tickets = [tn.tcrnet_submit(idx, q, k, ins) for q, k, ins in reqs]
         results = [tn.tcrnet_wait(idx, t) for t in tickets]
         final_deg = idx.degree()
         final_n = idx.size()
+        # merges of the base and the insert segments are published once
+        # their device work is done: a later query reads a merged base and
+        # at most the 5 insert segments a merge waits for, not 1 + 10
+        # segments
+        time.sleep(0.2)
+        last = tn.tcrnet_query(idx, q_last, 2)
+        assert last.info["parts"] <= 6, last.info
     order = np.argsort([r.info["seqno"] for r in results])
     snap = base
     new_edges = []
@@ -235,6 +253,8 @@ def test_paper_scale_resident_mixed_trace(tn, ctx, orc):
             assert np.array_equal(res.pairs, e), f"query {i}"
             assert np.array_equal(res.counts, c), f"query {i}"
     assert final_n == snap.n
+    e, c = orc.query(snap, q_last, 2)
+    assert np.array_equal(last.pairs, e) and np.array_equal(last.counts, c)
     # final degrees: the base network (k = 1 witness) plus every insert's edges
     _, d0 = orc.k1_build(base)
     deg = np.zeros(snap.n, dtype=np.int64)
@@ -250,9 +270,11 @@ def test_insert_failing_after_admission_never_leaves_a_torn_index(tn, orc):
     TCRNET_ENOMEM and the index is either unchanged (the failure came before
     the insert's sequences joined the repertoire; later requests are exact)
     or failed (every later call reports TCRNET_ESTATE) -- never a repertoire
-    with sequences whose edges and degrees are missing."""
+    with sequences whose edges and degrees are missing.  The insert is larger
+    than the 4,096 sequences a serving slot holds buffers for, so that it
+    still allocates after its sequences joined the repertoire."""
     base = synth.repertoire(2000, 200, 61)
-    new = synth.queries(300, 200, 61, 62)
+    new = synth.queries(5000, 200, 61, 62)
     _, d_base = orc.build(base, 1)
     sel, cnt, d_union = _insert_ref(orc, base, new, 1)
     lib = tn.load_library()
