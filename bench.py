@@ -10,23 +10,30 @@ sorted edge list + degrees).  Prints ONE JSON line.
   roofline       the pair kernel against the 32-bit VALU issue peak of
                  gfx950 (256 CU x 128 lanes x 2.4 GHz = 78.6 T lane-instr/s:
                  two waves of a SIMD issue plain 32-bit ops per 4 clocks);
-                 its algorithmic work = the text steps of the sorted-text walk
-                 with prefix-group jumps x 64 lanes x 12 VALU instructions per
-                 bit-vector step (13 where two 16-bit patterns share a lane;
-                 wave steps counted exactly by the CPU work model in
-                 bench_model.json)
+                 its algorithmic work = the wave text steps of its walk x 64
+                 lanes x 12 VALU instructions per bit-vector step (13 where
+                 two 16-bit patterns share a lane), the steps counted by the
+                 kernel's own counting variant at the timed schedule (and
+                 checked against the CPU work model in bench_model.json)
+  counters       issue, LDS and HBM counter figures of the same launch from
+                 bench_counters.json (rocprofv3 runs of this script), reported
+                 only while the pair kernel's sources are the ones they were
+                 taken with
+  medium         N = 50,000 (5,000 templates) at k = 1 and k = 2
   cpu_baseline   the CPU oracle (full DP, all host cores) on a bounded sample
-                 of rows of the same workload
+                 of rows of the same workload, with the host's core count
   serve / batch  the served and batched forms (see their sections)
 
 Usage: python bench.py [--gpus 1] [--steps 5] [--warmup 2]
+       python bench.py --ingest-counters DIR   (rocprofv3 CSVs -> bench_counters.json)
 """
 from __future__ import annotations
 
 import argparse
+import csv
+import glob
 import hashlib
 import json
-import math
 import os
 import sys
 import time
@@ -43,6 +50,8 @@ WAVE = 64
 T_STEP_INSTR = 12                          # gfx950 VALU instructions per Myers/Hyyro step
 T_STEP_INSTR_PACKED = 13                   # the same with two 16-bit patterns per lane (one more)
 T_STEP_LOGICAL = 17                        # word operations of the published step
+COUNTER_SOURCES = ["paper_2112_06613_amd/csrc/pairs.hip", "paper_2112_06613_amd/csrc/common.h",
+                   "paper_2112_06613_amd/csrc/prep.hip"]
 
 
 def log(msg: str):
@@ -62,31 +71,6 @@ def source_sha1(files) -> str:
     return h.hexdigest()
 
 
-def counted_traffic(texts_per_item: int, peq_lds: int):
-    """HBM bytes per pair-kernel launch from the committed FETCH_SIZE /
-    WRITE_SIZE counts (bench_traffic.json), each scaled by what the same
-    counter reads for a device copy of known size; None once the kernel's
-    sources, the work-item size or the kernel variant differ from those the
-    counters were taken with."""
-    path = os.path.join(ROOT, "bench_traffic.json")
-    if not os.path.exists(path):
-        log("no HBM counter record: traffic not reported")
-        return None
-    with open(path) as f:
-        rec = json.load(f)
-    if source_sha1(rec["sources"]) != rec["sources_sha1"]:
-        log("pair kernel sources changed since the HBM counters were taken: traffic not reported")
-        return None
-    if texts_per_item != rec["texts_per_item"]:
-        log(f"HBM counters were taken at {rec['texts_per_item']} texts per item: traffic not reported")
-        return None
-    if peq_lds != rec["peq_lds"]:
-        log(f"HBM counters were taken with peq_lds={rec['peq_lds']}: traffic not reported")
-        return None
-    kib = 1024.0
-    return (rec["fetch_kib"] * kib * rec["fetch_scale"] + rec["write_kib"] * kib * rec["write_scale"])
-
-
 def evaluated_pairs(lengths: np.ndarray, k: int) -> int:
     cnt = np.bincount(lengths, minlength=34).astype(np.int64)
     tot = 0
@@ -98,7 +82,136 @@ def evaluated_pairs(lengths: np.ndarray, k: int) -> int:
     return tot
 
 
-def plain_build(tn, torch, seqs, k, steps, warmup, ctx):
+# ----------------------------------------------------------------- roofline
+def counted_work(tn, seqs, k, info) -> dict:
+    """Wave text steps of the pair kernel's walk at the schedule `info` ran
+    with, counted by the kernel's counting variant (one extra build outside
+    any timed region; the walk depends on the texts per item and packing)."""
+    flags = tn.TCRNET_F_COUNT_WORK | tn.TCRNET_F_NO_AUTOTUNE | (0 if info["pack"] else tn.TCRNET_F_NO_PACK)
+    with tn.Context(0, texts_per_item=info["texts_per_item"], flags=flags) as c:
+        g = tn.tcrnet_build(c, seqs, k)
+    gi = g.info
+    assert gi["work_counted"] == 1 and gi["texts_per_item"] == info["texts_per_item"]
+    return {"wave_steps": gi["wave_steps"], "wave_steps_packed": gi["wave_steps_packed"],
+            "visited_texts": gi["visited_texts"], "edges": int(len(g.pairs))}
+
+
+def roofline(work: dict, pair_ms: float) -> dict:
+    plain = work["wave_steps"] - work["wave_steps_packed"]
+    instr = WAVE * (plain * T_STEP_INSTR + work["wave_steps_packed"] * T_STEP_INSTR_PACKED)
+    achieved = instr / (pair_ms * 1e-3)
+    return {
+        "bound": "alu",
+        "achieved": achieved / 1e12,
+        "peak": PEAK_LANE_OPS / 1e12,
+        "unit": "T lane-instr/s",
+        "frac": achieved / PEAK_LANE_OPS,
+        "kernel": "k_pairs",
+        "work_per_unit": f"{WAVE} lanes x {T_STEP_INSTR} VALU instr per wave text step "
+                         f"({T_STEP_INSTR_PACKED} when two patterns share a lane)",
+        "units_per_launch": work["wave_steps"],
+        "units_packed": work["wave_steps_packed"],
+        "visited_wave_texts": work["visited_texts"],
+        "units_source": "counted by the pair kernel's counting variant at the timed schedule",
+        # the published step's 17 word operations per pattern and text step
+        # (a packed wave step covers 128 patterns)
+        "frac_logical_17op": (WAVE * T_STEP_LOGICAL * (plain + 2 * work["wave_steps_packed"])
+                              / (pair_ms * 1e-3) / PEAK_LANE_OPS),
+    }
+
+
+def counter_figures(pair_ms: float, E: int, schedule: dict):
+    """Issue, LDS and HBM figures of the timed launch from bench_counters.json
+    (None, with the reason logged, once the pair kernel's sources or the
+    schedule differ from the ones the counters were taken with)."""
+    path = os.path.join(ROOT, "bench_counters.json")
+    if not os.path.exists(path):
+        log("no counter record: counters not reported")
+        return None
+    with open(path) as f:
+        rec = json.load(f)
+    if source_sha1(rec["sources"]) != rec["sources_sha1"]:
+        log("pair kernel sources changed since the counters were taken: counters not reported")
+        return None
+    for key in ("texts_per_item", "peq_lds", "pack", "waves_per_simd"):
+        if rec["schedule"].get(key) != schedule.get(key):
+            log(f"counters were taken with {key}={rec['schedule'].get(key)}: counters not reported")
+            return None
+    c = rec["counters"]
+    t = pair_ms * 1e-3
+    fetch = c["FETCH_SIZE"] * 1024.0 * rec["fetch_scale"]
+    write = c["WRITE_SIZE"] * 1024.0 * rec["write_scale"]
+    return {
+        "F_issue_valu": c["SQ_INSTS_VALU"] * WAVE / t / PEAK_LANE_OPS,
+        "valu_per_unit": c["SQ_INSTS_VALU"] / rec["units"],
+        "salu_per_unit": c["SQ_INSTS_SALU"] / rec["units"],
+        "branch_per_unit": c["SQ_INSTS_BRANCH"] / rec["units"],
+        "smem_per_unit": c["SQ_INSTS_SMEM"] / rec["units"],
+        "scalar_issue_frac": c["SQ_INSTS_SALU"] * 4.0 / (t * 2.4e9 * 1024),
+        "wait_frac": c["SQ_WAIT_ANY"] / c["SQ_WAVE_CYCLES"] if c.get("SQ_WAVE_CYCLES") else None,
+        "lds_bank_conflict_per_lds_instr": (c["SQ_LDS_BANK_CONFLICT"] / c["SQ_INSTS_LDS"]
+                                            if c["SQ_INSTS_LDS"] else 0.0),
+        "hbm_read_bytes": fetch,
+        "hbm_write_bytes": write,
+        "hbm_write_GBps": write / t / 1e9,
+        "hbm_write_bytes_per_edge": write / E if E else None,
+        "hbm_GBps": (fetch + write) / t / 1e9,
+        "record": "bench_counters.json",
+    }
+
+
+def ingest_counters(src: str):
+    """Read the rocprofv3 counter CSVs of the profiling passes under `src`
+    (one subdirectory per pass, each from `python bench.py --profile-run`),
+    average the pair kernel's dispatches and write bench_counters.json."""
+    per = {}
+    calib = {}
+    for f in sorted(glob.glob(os.path.join(src, "**", "*counter_collection.csv"), recursive=True)):
+        with open(f) as fh:
+            rows = list(csv.DictReader(fh))
+        disp = {}
+        for r in rows:
+            name = r["Kernel_Name"]
+            d = disp.setdefault(r["Dispatch_Id"], {"name": name, "c": {}})
+            d["c"][r["Counter_Name"]] = d["c"].get(r["Counter_Name"], 0.0) + float(r["Counter_Value"])
+        for d in disp.values():
+            if "copyBuffer" in d["name"]:
+                for k, v in d["c"].items():
+                    calib.setdefault(k, []).append(v)
+            elif "k_pairs<" in d["name"] and d["name"].split("k_pairs<")[1].split(">")[0].endswith("false"):
+                for k, v in d["c"].items():
+                    per.setdefault(k, []).append(v)
+    if not per:
+        sys.exit(f"no pair-kernel dispatches under {src}")
+    counters = {k: float(np.mean(v)) for k, v in per.items()}
+    with open(os.path.join(src, "run.json")) as f:
+        run = json.load(f)
+    copy_kib = run["calib_copy_mib"] * 1024.0
+    rec = {
+        "kernel": run["kernel"],
+        "workload": run["workload"],
+        "schedule": run["schedule"],
+        "units": run["units"],
+        "edges": run["edges"],
+        "pair_kernel_ms": run["pair_kernel_ms"],
+        "sources": COUNTER_SOURCES,
+        "sources_sha1": source_sha1(COUNTER_SOURCES),
+        "counters": counters,
+        "dispatches": {k: len(v) for k, v in per.items()},
+        "fetch_scale": copy_kib / float(np.mean(calib["FETCH_SIZE"])),
+        "write_scale": copy_kib / float(np.mean(calib["WRITE_SIZE"])),
+        "calibration": f"one {run['calib_copy_mib']} MiB device-to-device copy: FETCH_SIZE "
+                       f"{np.mean(calib['FETCH_SIZE']):.1f} KiB, WRITE_SIZE {np.mean(calib['WRITE_SIZE']):.1f} KiB "
+                       f"for {copy_kib:.0f} KiB read and written",
+    }
+    with open(os.path.join(ROOT, "bench_counters.json"), "w") as f:
+        json.dump(rec, f, indent=1, sort_keys=True)
+        f.write("\n")
+    print(json.dumps(rec, indent=1, sort_keys=True))
+
+
+# ------------------------------------------------------------------- builds
+def device_build(tn, torch, seqs, k, steps, warmup, ctx):
     dev = torch.device("cuda", 0)
     chars = torch.from_numpy(seqs.chars).to(dev)
     offs = torch.from_numpy(seqs.offsets.astype(np.int64)).to(dev)
@@ -108,7 +221,7 @@ def plain_build(tn, torch, seqs, k, steps, warmup, ctx):
     stream = torch.cuda.current_stream()
     for i in range(warmup):
         E = tn.tcrnet_build_device(ctx, chars, offs, k, pairs, deg, stream)
-        log(f"warmup {i}: E={E} pair kernel {ctx.last_info()['pair_kernel_ms']:.2f} ms")
+        log(f"warmup {i}: E={E} pair kernel {ctx.last_info()['pair_kernel_ms']:.3f} ms")
     torch.cuda.synchronize()
     infos = []
     t0 = time.perf_counter()
@@ -117,8 +230,45 @@ def plain_build(tn, torch, seqs, k, steps, warmup, ctx):
         infos.append(ctx.last_info())
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
-    log(f"timed {steps} steps: {wall * 1e3 / steps:.2f} ms/step, E={E}")
+    log(f"timed {steps} steps: {wall * 1e3 / steps:.3f} ms/step, E={E}")
     return wall / steps, E, infos
+
+
+def medium_leg(tn, torch, ctx) -> dict:
+    """N = 50,000 at k = 1 and k = 2 (separate runs), device-resident."""
+    import synth
+
+    s = synth.medium()
+    n = s.n
+    out = {"n": n, "seed": synth.SEED_MEDIUM}
+    for k in (1, 2):
+        step_s, E, infos = device_build(tn, torch, s, k, 20, 3, ctx)
+        pk = float(np.median([i["pair_kernel_ms"] for i in infos]))
+        work = counted_work(tn, s, k, infos[-1])
+        assert work["edges"] == E
+        r = roofline(work, pk)
+        out[f"k{k}"] = {"ms_per_step": step_s * 1e3, "pair_kernel_ms": pk, "edges": int(E),
+                        "logical_pairs_per_s": n * (n - 1) // 2 / step_s,
+                        "evaluated_pairs_per_s": infos[-1]["evaluated_pairs"] / step_s,
+                        "edges_per_s": E / step_s,
+                        "roofline_frac": r["frac"], "units_per_launch": r["units_per_launch"],
+                        "schedule": {kk: infos[-1][kk] for kk in ("texts_per_item", "waves_per_simd", "peq_lds",
+                                                                   "pack")}}
+    return out
+
+
+def host_info() -> dict:
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    aff = len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity") else None
+    return {"cpu_count": os.cpu_count(), "affinity_cpus": aff, "cpu_model": model}
 
 
 def cpu_baseline(seqs, k, target_s: float) -> dict:
@@ -141,20 +291,29 @@ def cpu_baseline(seqs, k, target_s: float) -> dict:
         o.build(seqs, k, row_lo=0, row_hi=rows)
         dt = time.perf_counter() - t0
     pairs = sum(n - 1 - i for i in range(rows))
-    return {"value": pairs / dt, "unit": "pairs/s", "cores": o.threads(), "kind": "oracle",
-            "sample": f"rows 0..{rows - 1} of the N={n} k={k} workload against all later rows "
-                      f"({pairs} full-DP pairs, {dt:.1f} s)"}
+    out = {"value": pairs / dt, "unit": "pairs/s", "cores": o.threads(), "kind": "oracle",
+           "sample": f"rows 0..{rows - 1} of the N={n} k={k} workload against all later rows "
+                     f"({pairs} full-DP pairs, {dt:.1f} s)"}
+    out.update({"host_" + kk: v for kk, v in host_info().items()})
+    out["threads_used"] = o.threads()
+    return out
 
 
 def batch_leg(tn, ctx, reps, k: int = 1) -> dict:
-    """Many repertoires in one captured launch sequence vs. one plain build
-    per repertoire, back to back, on the same GPU (host inputs and outputs in
-    both cases)."""
+    """Many repertoires in one captured launch sequence, with the schedule
+    the autotuner picks for the batch shape, vs. one plain build per
+    repertoire, back to back, on the same GPU (host inputs and outputs in
+    both cases); the batched pair kernel priced like the plain one."""
     tot = sum(r.n for r in reps)
+    t0 = time.perf_counter()
+    tn.tcrnet_autotune_batch(ctx, reps, k)
+    t_tune = time.perf_counter() - t0
+    tuned = tn.tcrnet_autotune_get(ctx, True, tot, k)
     tn.tcrnet_build_batch(ctx, reps, k)          # warm-up (captures the graph)
     t0 = time.perf_counter()
     gs = tn.tcrnet_build_batch(ctx, reps, k)
     t_batch = time.perf_counter() - t0
+    binfo = ctx.last_info()
     for r in reps[:4]:
         tn.tcrnet_build(ctx, r, k)
     t0 = time.perf_counter()
@@ -164,63 +323,99 @@ def batch_leg(tn, ctx, reps, k: int = 1) -> dict:
     t_plain = time.perf_counter() - t0
     batch_edges = sum(len(g.pairs) for g in gs)
     assert batch_edges == plain_edges
+    # work of the batched walk at the schedule it ran with (counting variant)
+    flags = tn.TCRNET_F_COUNT_WORK | tn.TCRNET_F_NO_AUTOTUNE | (0 if binfo["pack"] else tn.TCRNET_F_NO_PACK)
+    with tn.Context(0, texts_per_item=binfo["texts_per_item"], flags=flags) as c:
+        tn.tcrnet_build_batch(c, reps, k)
+        ci = c.last_info()
     logical = sum(r.n * (r.n - 1) // 2 for r in reps)
-    return {"repertoires": len(reps), "total_sequences": tot, "k": k, "edges": batch_edges,
-            "batched_ms": t_batch * 1e3, "back_to_back_ms": t_plain * 1e3, "speedup": t_plain / t_batch,
-            "batched_pairs_per_s": logical / t_batch, "back_to_back_pairs_per_s": logical / t_plain}
+    out = {"repertoires": len(reps), "total_sequences": tot, "k": k, "edges": batch_edges,
+           "batched_ms": t_batch * 1e3, "back_to_back_ms": t_plain * 1e3, "speedup": t_plain / t_batch,
+           "batched_device_ms": binfo["build_ms"],
+           "batched_pairs_per_s": logical / t_batch, "back_to_back_pairs_per_s": logical / t_plain,
+           "evaluated_pairs": binfo["evaluated_pairs"],
+           "schedule": {kk: binfo[kk] for kk in ("texts_per_item", "waves_per_simd", "peq_lds", "pack", "tuned")},
+           "autotune_s": t_tune, "autotuned": tuned}
+    work = {"wave_steps": ci["wave_steps"], "wave_steps_packed": ci["wave_steps_packed"],
+            "visited_texts": ci["visited_texts"]}
+    # the batch's pair kernel time is not separated from its captured launch
+    # sequence; pricing the whole device time gives a lower bound of its frac
+    r = roofline(work, binfo["build_ms"])
+    out["roofline_frac_lower_bound"] = r["frac"]
+    out["units_per_launch"] = r["units_per_launch"]
+    return out
 
 
-def serve_leg(tn, ctx, rep, n_requests: int, log) -> dict:
+def serve_leg(tn, ctx, rep, n_requests: int, loads) -> dict:
     """Resident repertoire; Poisson arrivals of query batches of 1-4,096
-    sequences (k in {1, 2}), 20% of them inserts.  Saturation rate first
-    (all requests at once), then an open-loop run at half of it."""
+    sequences (log-uniform sizes, k in {1, 2}), 20% of them inserts.  The
+    saturation rate first (all requests at once), then an open-loop run at
+    each fraction of it, each on a fresh index."""
     import threading
 
     import synth
 
     T = 80000
-    idx = tn.tcrnet_index_create(ctx, rep, 1)
+    # the trace's sizes, thresholds, kinds and query seeds do not depend on
+    # the rate (only the arrival times scale), so the queries are drawn once
     trace = synth.request_trace(n_requests, 1.0)
     qs = [synth.queries(r.size, T, synth.SEED_PAPER, r.qseed) for r in trace]
-    # closed loop: everything submitted at once
+
+    idx = tn.tcrnet_index_create(ctx, rep, 1)
     t0 = time.perf_counter()
     ts = [tn.tcrnet_submit(idx, q, r.k, r.insert) for q, r in zip(qs, trace)]
     for t in ts:
         tn.tcrnet_wait(idx, t)
     sat = n_requests / (time.perf_counter() - t0)
+    idx.close()
     log(f"serve: saturation {sat:.1f} requests/s")
-    # open loop at half the saturation rate, fresh index
-    idx.close()
-    idx = tn.tcrnet_index_create(ctx, rep, 1)
-    rate = 0.5 * sat
-    trace = synth.request_trace(n_requests, rate)
-    qs = [synth.queries(r.size, T, synth.SEED_PAPER, r.qseed) for r in trace]
-    tickets = [None] * n_requests
+    out = {"requests_per_load": n_requests, "saturation_rate_hz": sat, "resident_start": rep.n, "index_k": 1,
+           "loads": {}}
+    for frac in loads:
+        idx = tn.tcrnet_index_create(ctx, rep, 1)
+        trace = synth.request_trace(n_requests, frac * sat)
+        tickets = [None] * n_requests
 
-    def submitter():
-        start = time.perf_counter()
-        for i, r in enumerate(trace):
-            delay = start + r.t_arrival - time.perf_counter()
-            if delay > 0:
-                time.sleep(delay)
-            tickets[i] = tn.tcrnet_submit(idx, qs[i], r.k, r.insert)
+        def submitter():
+            start = time.perf_counter()
+            for i, r in enumerate(trace):
+                delay = start + r.t_arrival - time.perf_counter()
+                if delay > 0:
+                    time.sleep(delay)
+                tickets[i] = tn.tcrnet_submit(idx, qs[i], r.k, r.insert)
 
-    th = threading.Thread(target=submitter)
-    t0 = time.perf_counter()
-    th.start()
-    th.join()
-    res = [tn.tcrnet_wait(idx, t) for t in tickets]
-    wall = time.perf_counter() - t0
-    lat = np.array([r.info["latency_ms"] for r in res])
-    dev = np.array([r.info["device_ms"] for r in res])
-    nq = sum(r.size for r in trace)
-    final = idx.size()
-    idx.close()
-    return {"requests": n_requests, "offered_rate_hz": rate, "saturation_rate_hz": sat,
-            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-            "mean_device_ms": float(dev.mean()), "requests_per_s": n_requests / wall,
-            "query_seqs_per_s": nq / wall, "inserts": int(sum(r.insert for r in trace)),
-            "resident_start": rep.n, "resident_end": final, "index_k": 1}
+        th = threading.Thread(target=submitter)
+        t0 = time.perf_counter()
+        th.start()
+        th.join()
+        res = [tn.tcrnet_wait(idx, t) for t in tickets]
+        wall = time.perf_counter() - t0
+        final = idx.size()
+        idx.close()
+        lat = np.array([r.info["latency_ms"] for r in res])
+        dev = np.array([r.info["device_ms"] for r in res])
+        que = np.array([r.info["queue_ms"] for r in res])
+        size = np.array([r.size for r in trace])
+        ks = np.array([r.k for r in trace])
+        ins = np.array([r.insert for r in trace])
+        slow = lat >= np.percentile(lat, 99)
+        rec = {"offered_rate_hz": frac * sat, "p50_ms": float(np.percentile(lat, 50)),
+               "p99_ms": float(np.percentile(lat, 99)), "mean_device_ms": float(dev.mean()),
+               "requests_per_s": n_requests / wall, "query_seqs_per_s": float(size.sum()) / wall,
+               "inserts": int(ins.sum()), "resident_end": final,
+               # what the slowest 1% were: time in the queue vs on the device,
+               # and their size, threshold and kind
+               "p99_tail": {"n": int(slow.sum()), "mean_queue_ms": float(que[slow].mean()),
+                            "mean_device_ms": float(dev[slow].mean()),
+                            "mean_size": float(size[slow].mean()), "frac_k2": float((ks[slow] == 2).mean()),
+                            "frac_insert": float(ins[slow].mean())}}
+        for name, sel in (("k1", ks == 1), ("k2", ks == 2), ("insert", ins), ("size_lt_64", size < 64),
+                          ("size_ge_1024", size >= 1024)):
+            if sel.any():
+                rec[f"p99_ms_{name}"] = float(np.percentile(lat[sel], 99))
+        out["loads"][str(frac)] = rec
+        log(f"serve at {frac} x saturation: p50 {rec['p50_ms']:.3f} ms, p99 {rec['p99_ms']:.3f} ms")
+    return out
 
 
 def host_to_host(tn, ctx, seqs, k) -> dict:
@@ -271,12 +466,19 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--no-batch", action="store_true")
+    ap.add_argument("--no-medium", action="store_true")
     ap.add_argument("--autotune", action="store_true")
     ap.add_argument("--no-analysis", action="store_true")
-    ap.add_argument("--serve-requests", type=int, default=400)
-    ap.add_argument("--calib-copy-mib", type=int, default=0,
-                    help="run one device copy of this size first (HBM counter calibration)")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--profile-run", metavar="DIR", default=None,
+                    help="only the timed plain builds, after one device copy of --calib-copy-mib MiB "
+                         "(HBM counter calibration); the run's schedule and work go to DIR/run.json")
+    ap.add_argument("--calib-copy-mib", type=int, default=256)
+    ap.add_argument("--ingest-counters", metavar="DIR", default=None)
     args = ap.parse_args()
+    if args.ingest_counters:
+        ingest_counters(args.ingest_counters)
+        return
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
               "the path is not sharded across GPUs", file=sys.stderr)
@@ -289,7 +491,13 @@ def main():
 
     tn.load_library()
     log(f"library {tn.version()}, device {torch.cuda.get_device_name(0)}")
-    if args.calib_copy_mib:
+
+    k = 1
+    seqs = synth.paper_scale()
+    n = seqs.n
+    ev_pairs = evaluated_pairs(seqs.lengths(), k)
+    ctx = tn.Context(0)
+    if args.profile_run:
         nb = args.calib_copy_mib << 20
         a = torch.empty(nb // 4, dtype=torch.int32, device="cuda")
         b = torch.empty_like(a)
@@ -298,33 +506,47 @@ def main():
         b.copy_(a)
         torch.cuda.synchronize()
         del a, b
-        log(f"calibration copy of {args.calib_copy_mib} MiB done")
-
-    k = 1
-    seqs = synth.paper_scale()
-    n = seqs.n
-    model = load_model("paper_n800000_k1")
-    ev_pairs = evaluated_pairs(seqs.lengths(), k)
-    assert ev_pairs == model["evaluated_pairs"]
-    ctx = tn.Context(0)
+        step_s, E, infos = device_build(tn, torch, seqs, k, args.steps, 0, ctx)
+        pk = float(np.mean([i["pair_kernel_ms"] for i in infos]))
+        sched = {kk: infos[-1][kk] for kk in ("texts_per_item", "waves_per_simd", "peq_lds", "pack")}
+        ctx.close()
+        work = counted_work(tn, seqs, k, infos[-1])
+        os.makedirs(args.profile_run, exist_ok=True)
+        with open(os.path.join(args.profile_run, "run.json"), "w") as f:
+            json.dump({"kernel": "k_pairs<%s, %d, false>" % ("true" if sched["peq_lds"] else "false", k),
+                       "workload": "plain network build, N=800,000 synthetic CDR3b, k=1",
+                       "schedule": sched, "units": work["wave_steps"], "edges": int(E), "pair_kernel_ms": pk,
+                       "calib_copy_mib": args.calib_copy_mib}, f, indent=1)
+        log(f"profile run: pair kernel {pk:.3f} ms, {work['wave_steps']} wave steps")
+        return
     if args.autotune:
         tn.tcrnet_autotune(ctx, seqs, k)
     peak_meas, peak_s = tn.tcrnet_valu_peak(ctx)
     log(f"measured VALU issue rate {peak_meas / 1e12:.2f} T lane-instr/s ({peak_s * 1e3:.1f} ms probe)")
-    step_s, E, infos = plain_build(tn, torch, seqs, k, args.steps, args.warmup, ctx)
+    step_s, E, infos = device_build(tn, torch, seqs, k, args.steps, args.warmup, ctx)
     pk_ms = float(np.mean([i["pair_kernel_ms"] for i in infos]))
     assert all(i["evaluated_pairs"] == ev_pairs for i in infos)
+    schedule = {kk: infos[-1][kk] for kk in ("texts_per_item", "waves_per_simd", "peq_lds", "pack")}
+    log("counting the pair kernel's work ...")
+    work = counted_work(tn, seqs, k, infos[-1])
+    assert work["edges"] == E
+    rl = roofline(work, pk_ms)
+    cf = counter_figures(pk_ms, E, schedule)
+    rl["traffic"] = (cf["hbm_read_bytes"] + cf["hbm_write_bytes"]) if cf else None
+    rl["traffic_unit"] = "B per launch"
+    rl["peak_measured"] = peak_meas / 1e12
+    rl["frac_of_measured"] = rl["achieved"] * 1e12 / peak_meas
+    # the CPU work model of the same walk (bench_model.json), where it was
+    # computed at this schedule
+    model = load_model("paper_n800000_k1")
+    assert ev_pairs == model["evaluated_pairs"]
     trav = model["traversal"]
-    T_used = infos[-1]["texts_per_item"]
-    pack_used = bool(infos[-1]["pack"])
-    priced = T_used == trav["texts_per_item"] and pack_used == trav["pack"]
-    if not priced:
-        log(f"schedule (T={T_used}, pack={pack_used}) differs from the work model's "
-            f"(T={trav['texts_per_item']}, pack={trav['pack']}): roofline not priced")
-    plain_steps = trav["wave_steps"] - trav["wave_steps_packed"]
-    work_instr = WAVE * (plain_steps * T_STEP_INSTR + trav["wave_steps_packed"] * T_STEP_INSTR_PACKED)
-    achieved = work_instr / (pk_ms * 1e-3)
+    if trav["texts_per_item"] == schedule["texts_per_item"] and trav["pack"] == bool(schedule["pack"]):
+        rl["units_model"] = trav["wave_steps"]
+        rl["units_model_agrees"] = trav["wave_steps"] == work["wave_steps"]
     pair_work = ev_pairs * model["mean_exit_steps"] * T_STEP_INSTR
+    rl["per_pair_work_lane_instr"] = pair_work
+    rl["traversal_saving"] = pair_work / (rl["achieved"] * 1e12 * pk_ms * 1e-3)
     logical = n * (n - 1) // 2
     out = {
         "metric": METRIC,
@@ -347,36 +569,16 @@ def main():
         "evaluated_pairs": ev_pairs,
         "evaluated_pairs_per_s": ev_pairs / step_s,
         "pair_kernel_ms": pk_ms,
-        "schedule": {kk: infos[-1][kk] for kk in ("texts_per_item", "waves_per_simd", "peq_lds", "pack")},
-        "roofline": {
-            "bound": "alu",
-            "achieved": achieved / 1e12 if priced else None,
-            "peak": PEAK_LANE_OPS / 1e12,
-            "unit": "T lane-instr/s",
-            "frac": achieved / PEAK_LANE_OPS if priced else None,
-            "traffic": counted_traffic(T_used, infos[-1]["peq_lds"]),
-            "traffic_unit": "B per launch",
-            "kernel": "k_pairs",
-            "work_per_unit": f"{WAVE} lanes x {T_STEP_INSTR} VALU instr per wave text step "
-                             f"({T_STEP_INSTR_PACKED} when two patterns share a lane)",
-            "units_per_launch": trav["wave_steps"],
-            "units_packed": trav["wave_steps_packed"],
-            "visited_wave_texts": trav["visited_texts"],
-            # the published step's 17 word operations per pattern and text step
-            # (a packed wave step covers 128 patterns)
-            "frac_logical_17op": (WAVE * T_STEP_LOGICAL * (plain_steps + 2 * trav["wave_steps_packed"])
-                                  / (pk_ms * 1e-3) / PEAK_LANE_OPS) if priced else None,
-            "peak_measured": peak_meas / 1e12,
-            "frac_of_measured": achieved / peak_meas if priced else None,
-            "per_pair_work_lane_instr": pair_work,
-            "traversal_saving": pair_work / work_instr,
-            # every kept pair priced at its own exit step, per second, over the
-            # peak: above 1 because the walk skips most of that work
-            "frac_pair_work": pair_work / (pk_ms * 1e-3) / PEAK_LANE_OPS,
-        },
+        "build_device_ms": float(np.mean([i["build_ms"] for i in infos])),
+        "schedule": schedule,
+        "roofline": rl,
+        "counters": cf,
     }
     log("host-to-host build ...")
     out["host_to_host"] = host_to_host(tn, ctx, seqs, k)
+    if not args.no_medium:
+        log("N = 50,000 at k = 1 and 2 ...")
+        out["medium"] = medium_leg(tn, torch, ctx)
     if not args.no_analysis:
         log("network analysis ...")
         out["analysis"] = analysis_leg(tn, ctx, seqs, k)
@@ -385,7 +587,7 @@ def main():
         out["batch"] = batch_leg(tn, ctx, synth.batch())
     if not args.no_serve:
         log("served form ...")
-        out["serve"] = serve_leg(tn, ctx, seqs, args.serve_requests, log)
+        out["serve"] = serve_leg(tn, ctx, seqs, args.serve_requests, (0.25, 0.5, 0.8))
         out["serve"]["plain_rebuild_ms"] = step_s * 1e3
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
