@@ -59,10 +59,13 @@ __host__ __device__ inline uint64_t sorted_rec_bytes(uint64_t n) {
   return n * sizeof(SeqRec) + (uint64_t)kWalkDepth * (n + 1) * sizeof(WalkEnt);
 }
 
-// Bit masks of one pattern: eq[c] has bit q set iff residue q has code c
-// (Myers' Peq table).  80 bytes.
+// The residue codes of one pattern as bit planes: bit q of pl[b] is bit b of
+// residue q's code (positions past the length hold code 0).  Myers' Peq
+// table follows from them: eq[c] = AND over b of (pl[b] or its complement, as
+// bit b of c is 1 or 0), restricted to the length.  20 bytes: a work item's
+// patterns are read as planes and their tables built in registers.
 struct PeqRec {
-  uint32_t eq[kAlpha];
+  uint32_t pl[5];
 };
 
 // One pair of length buckets (pattern bucket of length m, text bucket of

@@ -221,15 +221,27 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     if (d.tri && tb < gbase + 1) tb = gbase + 1;
     if (tb >= te) return;  // a diagonal chunk wholly before the group's patterns
 
+    const uint32_t m = d.m, n = d.n;  // m >= n: the pattern is the longer string
+    const uint32_t Mm = kPack == 2 ? low_mask(m) * 0x10001u : low_mask(m);
+    // Myers' Peq table of the lane's pattern(s), built from their bit planes:
+    // eq[a] = positions whose code is a (within the length)
     uint32_t eq[kAlpha];
     {
       const PeqRec pr = load_global(ppeq, p0);
+      uint32_t pl[5];
 #pragma unroll
-      for (int a = 0; a < kAlpha; ++a) eq[a] = pr.eq[a];
+      for (int b = 0; b < 5; ++b) pl[b] = pr.pl[b];
       if constexpr (kPack == 2) {
         const PeqRec ph = load_global(ppeq, p1);
 #pragma unroll
-        for (int a = 0; a < kAlpha; ++a) eq[a] |= ph.eq[a] << 16;
+        for (int b = 0; b < 5; ++b) pl[b] |= ph.pl[b] << 16;
+      }
+#pragma unroll
+      for (int a = 0; a < kAlpha; ++a) {
+        uint32_t e = Mm;
+#pragma unroll
+        for (int b = 0; b < 5; ++b) e &= ((a >> b) & 1) ? pl[b] : ~pl[b];
+        eq[a] = e;
       }
     }
     if (kPeqLds) {
@@ -238,9 +250,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
       __builtin_amdgcn_wave_barrier();
     }
 
-    const uint32_t m = d.m, n = d.n;  // m >= n: the pattern is the longer string
     const uint32_t delta = m - n;     // final diagonal: row = column + delta
-    const uint32_t Mm = kPack == 2 ? low_mask(m) * 0x10001u : low_mask(m);
     // Miss word: bit delta+J set when text step J missed on the final
     // diagonal, bits below delta set from the start, so popcount(Z) is the
     // diagonal cell D[delta+j][j] after j steps and D[m][n] = lev at the end

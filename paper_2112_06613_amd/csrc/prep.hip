@@ -220,7 +220,7 @@ __global__ void k_gather(const SeqRec* __restrict__ rec, const uint32_t* __restr
       if (s + 1 == n) walk[(uint64_t)d * (n + 1) + n] = WalkEnt{8u * (uint32_t)n, 0u};  // the extra entry
     }
   }
-  // bit planes of the residue codes, then Peq[c] = positions whose code is c
+  // bit planes of the residue codes
   uint32_t pl[5] = {0, 0, 0, 0, 0};
 #pragma unroll
   for (int q = 0; q < kMaxLen; ++q) {
@@ -228,16 +228,9 @@ __global__ void k_gather(const SeqRec* __restrict__ rec, const uint32_t* __restr
 #pragma unroll
     for (int b = 0; b < 5; ++b) pl[b] |= ((c >> b) & 1u) << q;
   }
-  const uint32_t len = r.len & kLenMask;
-  const uint32_t lm = len >= 32 ? ~0u : ((1u << len) - 1u);
   PeqRec p;
 #pragma unroll
-  for (int c = 0; c < kAlpha; ++c) {
-    uint32_t eq = lm;
-#pragma unroll
-    for (int b = 0; b < 5; ++b) eq &= ((c >> b) & 1) ? pl[b] : ~pl[b];
-    p.eq[c] = eq;
-  }
+  for (int b = 0; b < 5; ++b) p.pl[b] = pl[b];
   speq[s] = p;
 }
 
