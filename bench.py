@@ -198,10 +198,12 @@ def ingest_counters(src: str):
         "sources_sha1": source_sha1(COUNTER_SOURCES),
         "counters": counters,
         "dispatches": {k: len(v) for k, v in per.items()},
-        "fetch_scale": copy_kib / float(np.mean(calib["FETCH_SIZE"])),
-        "write_scale": copy_kib / float(np.mean(calib["WRITE_SIZE"])),
+        # the calibration copy is the largest copy kernel of the run (the
+        # run's other copies move its inputs and are far smaller)
+        "fetch_scale": copy_kib / float(np.max(calib["FETCH_SIZE"])),
+        "write_scale": copy_kib / float(np.max(calib["WRITE_SIZE"])),
         "calibration": f"one {run['calib_copy_mib']} MiB device-to-device copy: FETCH_SIZE "
-                       f"{np.mean(calib['FETCH_SIZE']):.1f} KiB, WRITE_SIZE {np.mean(calib['WRITE_SIZE']):.1f} KiB "
+                       f"{np.max(calib['FETCH_SIZE']):.1f} KiB, WRITE_SIZE {np.max(calib['WRITE_SIZE']):.1f} KiB "
                        f"for {copy_kib:.0f} KiB read and written",
     }
     with open(os.path.join(ROOT, "bench_counters.json"), "w") as f:
