@@ -3,6 +3,8 @@
 // captured in a HIP graph).
 #include "pipeline.h"
 
+#include <rocprofiler-sdk-roctx/roctx.h>
+
 #include <atomic>
 #include <cstdio>
 
@@ -11,6 +13,15 @@ namespace tcr {
 namespace {
 thread_local std::string g_last_error;
 std::atomic<int64_t> g_fail_after{-1};  // successful allocations before an injected failure (-1: none)
+
+// roctx range over the host-side launch sequence of one stage (shown by
+// rocprofv3 --marker-trace beside the kernels the stage enqueues).
+struct StageRange {
+  explicit StageRange(const char* name) { roctxRangePushA(name); }
+  ~StageRange() { roctxRangePop(); }
+  StageRange(const StageRange&) = delete;
+  StageRange& operator=(const StageRange&) = delete;
+};
 
 bool injected_failure() {
   int64_t v = g_fail_after.load();
@@ -125,6 +136,7 @@ hipError_t pipeline_reserve(Pipeline& pl, uint64_t n, uint32_t n_seg, int k, uin
 
 void stage_prepare(Pipeline& pl, const char* d_data, const uint64_t* d_off, uint32_t n, const uint32_t* d_segoff,
                    uint32_t n_seg, uint32_t id_base, uint32_t id_tag, const SetOut& out, hipStream_t st) {
+  StageRange range("tcrnet:prepare");
   const uint32_t seg_bits = seg_bits_for(n_seg);
   SeqRec* srec = out.srec ? out.srec : pl.srec.as<SeqRec>();
   PeqRec* speq = out.speq ? out.speq : pl.speq.as<PeqRec>();
@@ -146,6 +158,7 @@ void stage_prepare(Pipeline& pl, const char* d_data, const uint64_t* d_off, uint
 }
 
 void stage_prepare_records(Pipeline& pl, const SeqRec* rec, uint32_t n, const SetOut& out, hipStream_t st) {
+  StageRange range("tcrnet:prepare_records");
   SeqRec* srec = out.srec ? out.srec : pl.srec.as<SeqRec>();
   PeqRec* speq = out.speq ? out.speq : pl.speq.as<PeqRec>();
   uint32_t* off = out.off ? out.off : pl.off.as<uint32_t>();
@@ -166,6 +179,7 @@ void stage_prepare_records(Pipeline& pl, const SeqRec* rec, uint32_t n, const Se
 void stage_pairs(Pipeline& pl, const PlanPart* d_parts, uint32_t n_parts, const PlanPart& inline_part, int k,
                  const Sched& sched, uint64_t capacity, uint32_t grid_blocks, hipStream_t st, hipEvent_t ev0,
                  hipEvent_t ev1, bool keep_dist) {
+  StageRange range("tcrnet:pairs");
   Counters* cnt = pl.cnt();
   launch_reset_work(cnt, st);
   launch_plan(d_parts, n_parts, inline_part, k, sched.texts_per_item, sched.pack, pl.descs.as<Desc>(),
@@ -189,6 +203,7 @@ void stage_pairs(Pipeline& pl, const PlanPart* d_parts, uint32_t n_parts, const 
 
 void stage_canon(Pipeline& pl, int mode, int shift, uint64_t capacity, uint32_t* d_pairs, int32_t* d_deg,
                  hipStream_t st, uint8_t* d_dist) {
+  StageRange range("tcrnet:canonicalise");
   Counters* cnt = pl.cnt();
   launch_edge_keys(pl.edges.as<uint32_t>(), d_dist ? pl.edist.as<uint8_t>() : nullptr, capacity, &cnt->edges, mode,
                    shift, pl.ekeys.as<uint64_t>(), st);
