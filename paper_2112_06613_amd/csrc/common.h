@@ -126,10 +126,30 @@ struct Plan {
 
 // Work counters of one build (zeroed before the encode kernel).  Every wave
 // takes work items with atomics, so the queue is split into kQueueStripes
-// counters (stripe s hands out items s, s + kQueueStripes, ...), each on a
-// cache line of its own, and the edge counter sits on another: the atomics
-// of thousands of waves do not serialise on one line.
-constexpr int kQueueStripes = 16;
+// counters, each on a cache line of its own, and the edge counter sits on
+// another: the atomics of thousands of waves do not serialise on one line.
+// The items are dealt out in blocks of consecutive items (which mostly share
+// one chunk of texts), block b to XCD b mod kXcds; the XCD's two stripes take
+// alternate items of its blocks in increasing order.  A chunk's texts are
+// then read by the waves of one XCD, from its own L2, and every XCD still
+// works through the plan's order (largest items first).  The block is the
+// largest power of two from 256 to 1,024 items that leaves every XCD at least
+// 32 blocks (a short tail); launches of fewer than 65,536 items, whose texts
+// fit the L2s anyway, take blocks of one item (plain striping: stripe s hands
+// out items 16j + 8(s mod 2) + s/2).
+constexpr int kXcds = 8;  // MI355X: 8 XCDs of 32 CUs, workgroups dealt round-robin
+constexpr int kQueueStripes = 2 * kXcds;
+__host__ __device__ inline uint32_t queue_block_log2(uint64_t total_items) {
+  if (total_items < (1u << 16)) return 0;
+  uint32_t l = 8;
+  while (l < 10 && (total_items >> (l + 1)) >= 32u * kXcds) ++l;
+  return l;
+}
+__host__ __device__ inline uint64_t queue_item(uint32_t stripe, uint64_t j, uint32_t block_log2) {
+  const uint64_t jj = 2 * j + (stripe & 1u);  // the XCD's jj-th item
+  const uint64_t mask = (1ull << block_log2) - 1ull;
+  return ((((jj >> block_log2) * kXcds) + stripe / 2) << block_log2) + (jj & mask);
+}
 struct alignas(128) QueueLine {
   unsigned long long next;        // next index j of this stripe
   unsigned long long pad[15];

@@ -481,16 +481,20 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
 #undef TCR_CODE
   };
 
-  // a wave starts on its own queue stripe and moves on when it runs dry; it
-  // stops after finding every stripe empty in a row
-  uint32_t stripe = (blockIdx.x * (kBlock / kWave) + rfl(wid)) % kQueueStripes;
+  // a wave starts on a stripe of its own XCD (workgroups are dealt to the
+  // XCDs round-robin) when items go to XCDs in blocks, else the four waves of
+  // a workgroup start on four different stripes; a wave moves on when its
+  // stripe runs dry and stops after finding every stripe empty in a row
+  const uint32_t qlog = queue_block_log2(total);
+  uint32_t stripe = qlog ? 2u * (blockIdx.x % (uint32_t)kXcds) + (rfl(wid) & 1u)
+                         : (blockIdx.x * (kBlock / kWave) + rfl(wid)) % kQueueStripes;
   uint32_t empty = 0;
   uint32_t dcache = 0;  // descriptor of the wave's previous item
   for (;;) {
     uint64_t j = 0;
     if (lane == 0) j = atomicAdd(&cnt->queue[stripe].next, 1ull);
     j = rfl64(j);
-    const uint64_t item = j * kQueueStripes + stripe;
+    const uint64_t item = queue_item(stripe, j, qlog);
     if (item >= total) {
       if (++empty == (uint32_t)kQueueStripes) break;
       stripe = (stripe + 1) % kQueueStripes;
