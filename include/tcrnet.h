@@ -91,7 +91,7 @@ typedef struct {
                                from N); too small only costs one re-run */
   uint64_t hbm_budget;      /* serving: bytes of device memory that admitted
                                requests may hold at once (0: 1/4 of free) */
-  uint32_t max_inflight;    /* serving: requests on the device at once (0: 8) */
+  uint32_t max_inflight;    /* serving: requests on the device at once (0: 4) */
   uint32_t flags;           /* TCRNET_F_* */
 } tcrnet_opts;
 
