@@ -107,9 +107,26 @@ typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
 __device__ __forceinline__ uint32_t pk_add(uint32_t a, uint32_t b) {
   return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, a) + __builtin_bit_cast(u16x2, b));
 }
-__device__ __forceinline__ uint32_t pk_dec(uint32_t a) {
-  const u16x2 one = {1, 1};
-  return __builtin_bit_cast(uint32_t, __builtin_bit_cast(u16x2, a) - one);
+
+// kPack: 1, one pattern per lane; 2, two per lane with 16-bit packed adds
+// (patterns of 16 residues); 3, two per lane for patterns of at most 15
+// residues, with plain 32-bit adds.  v_pk_add_u16 issues at half the rate of
+// v_add_u32 on gfx950, and with at most 15 residues no plain add carries
+// across the halves: bit 15 of Eq is clear, and VP is kept masked to the
+// pattern's bits after every step, so (Eq & VP) + VP stays below 2^16 in each
+// half and the doubling of HN = D0 & VP cannot reach bit 16; the doubling of
+// HP may move a bit into bit 16 of X, which the step sets anyway.  The bits
+// of a half above the pattern (which the add and the doubling can set) never
+// flow down into the pattern's bits, as in the one-pattern form.
+template <int kPack>
+__device__ __forceinline__ uint32_t add_p(uint32_t a, uint32_t b) {
+  if constexpr (kPack == 2) return pk_add(a, b);
+  else return a + b;
+}
+template <int kPack>
+__device__ __forceinline__ uint32_t dbl_p(uint32_t x) {
+  if constexpr (kPack == 2) return pk_add(x, x);
+  else return twice(x);
 }
 
 // popcount(z) <= k for one miss word, with the cheap forms for k = 1 (at
@@ -126,14 +143,18 @@ __device__ __forceinline__ bool within_k_word(uint32_t z, int k) {
 
 // The lane has a pattern still within k: the word, or either 16-bit half of
 // a two-pattern word (a half is zero after clearing its lowest k set bits).
+// The halves' lowest set bits are cleared with one 32-bit subtraction of
+// 0x10001 (twice the issue rate of a packed one): it borrows from the upper
+// half only when the lower half is zero, and then the lane is within k
+// whatever the upper half holds.
 template <int kMode, int kPack>
 __device__ __forceinline__ bool within_k_lane(uint32_t z, int k) {
   if constexpr (kPack == 1) {
     return within_k_word<kMode>(z, k);
   } else {
     if (kMode == 1 || kMode == 2) {
-      uint32_t y = z & pk_dec(z);
-      if (kMode == 2) y &= pk_dec(y);
+      uint32_t y = z & (z - 0x10001u);
+      if (kMode == 2) y &= y - 0x10001u;
       return min(y & 0xFFFFu, y >> 16) == 0u;
     }
     return (int)min(__popc(z & 0xFFFFu), __popc(z >> 16)) <= k;
@@ -204,7 +225,8 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
   // against text chunk c of descriptor d.
   auto run_item = [&](auto pack_tag, const Desc& d, uint32_t g, uint32_t c) {
     constexpr int kPack = decltype(pack_tag)::value;
-    constexpr uint32_t kGroup = kWave * kPack;  // patterns of a work item
+    constexpr bool kTwo = kPack >= 2;           // two patterns per lane
+    constexpr uint32_t kGroup = kWave * (kTwo ? 2 : 1);  // patterns of a work item
     const SeqRec* prec = d.prec;
     const PeqRec* ppeq = d.ppeq;
     const SeqRec* trec = d.trec;
@@ -212,7 +234,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     // lane's patterns: gbase + lane (bits 0-15 when packed), gbase + 64 + lane
     // (bits 16-31); a lane outside the item reads pattern d.p0 and is masked
     const bool ok0 = g * kGroup + lane < d.np;
-    const bool ok1 = kPack == 2 && g * kGroup + kWave + lane < d.np;
+    const bool ok1 = kTwo && g * kGroup + kWave + lane < d.np;
     const uint32_t p0 = ok0 ? gbase + lane : d.p0;
     const uint32_t p1 = ok1 ? gbase + kWave + lane : d.p0;
     const uint32_t tb0 = d.t0 + c * d.T;
@@ -222,7 +244,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     if (tb >= te) return;  // a diagonal chunk wholly before the group's patterns
 
     const uint32_t m = d.m, n = d.n;  // m >= n: the pattern is the longer string
-    const uint32_t Mm = kPack == 2 ? low_mask(m) * 0x10001u : low_mask(m);
+    const uint32_t Mm = kTwo ? low_mask(m) * 0x10001u : low_mask(m);
     // Myers' Peq table of the lane's pattern(s), built from their bit planes:
     // eq[a] = positions whose code is a (within the length)
     uint32_t eq[kAlpha];
@@ -231,7 +253,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
       uint32_t pl[5];
 #pragma unroll
       for (int b = 0; b < 5; ++b) pl[b] = pr.pl[b];
-      if constexpr (kPack == 2) {
+      if constexpr (kTwo) {
         const PeqRec ph = load_global(ppeq, p1);
 #pragma unroll
         for (int b = 0; b < 5; ++b) pl[b] |= ph.pl[b] << 16;
@@ -257,7 +279,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     // (per 16-bit half when packed).  A pattern outside the item starts with
     // all its bits set (never within k).
     uint32_t z_item, m_item;
-    if constexpr (kPack == 2) {
+    if constexpr (kTwo) {
       z_item = (ok0 ? (1u << delta) - 1u : 0xFFFFu) | ((ok1 ? (1u << delta) - 1u : 0xFFFFu) << 16);
       m_item = (1u << delta) * 0x10001u;
     } else {
@@ -273,11 +295,11 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     // Edges of the patterns whose final miss word fZ is within k, against
     // every text of [t_first, t_end) (a run of identical texts).
     auto emit = [&](uint32_t fZ, uint32_t t_first, uint32_t t_end) {
-      const uint32_t fz0 = kPack == 2 ? fZ & 0xFFFFu : fZ;
+      const uint32_t fz0 = kTwo ? fZ & 0xFFFFu : fZ;
       const bool hit0 = within_k_word<kMode>(fz0, k);
-      const bool hit1 = kPack == 2 && within_k_word<kMode>(fZ >> 16, k);
+      const bool hit1 = kTwo && within_k_word<kMode>(fZ >> 16, k);
       const uint64_t hm0 = __ballot(hit0);
-      const uint64_t hm1 = kPack == 2 ? __ballot(hit1) : 0ull;
+      const uint64_t hm1 = kTwo ? __ballot(hit1) : 0ull;
       if (!(hm0 | hm1)) return;
       const uint32_t nh0 = (uint32_t)__popcll(hm0);
       const uint32_t nh = nh0 + (uint32_t)__popcll(hm1);
@@ -312,13 +334,14 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
   {                                                                            \
     const uint32_t Eq = TCR_EQ(code);                                          \
     uint32_t D0;                                                               \
-    if constexpr (kPack == 2) {                                                \
-      D0 = (pk_add(Eq & VP, VP) ^ VP) | Eq | VN;                               \
+    if constexpr (kTwo) {                                                      \
+      D0 = (add_p<kPack>(Eq & VP, VP) ^ VP) | Eq | VN;                         \
       const uint32_t HP = VN | ~(D0 | VP);                                     \
       const uint32_t HN = D0 & VP;                                             \
-      const uint32_t X = pk_add(HP, HP) | 0x00010001u;                         \
+      const uint32_t X = dbl_p<kPack>(HP) | 0x00010001u;                       \
       VN = X & D0;                                                             \
-      VP = pk_add(HN, HN) | ~(X | D0);                                         \
+      VP = dbl_p<kPack>(HN) | ~(X | D0);                                       \
+      if constexpr (kPack == 3) VP &= Mm;                                      \
     } else {                                                                   \
       D0 = (((Eq & VP) + VP) ^ VP) | Eq | VN;                                  \
       const uint32_t HP = VN | ~(D0 | VP);                                     \
@@ -331,7 +354,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     alive = __ballot((within_k_lane<kMode, kPack>(Z, k))) != 0ull;             \
     if constexpr (kCount) {                                                    \
       ++n_steps;                                                               \
-      if constexpr (kPack == 2) ++n_steps_packed;                              \
+      if constexpr (kTwo) ++n_steps_packed;                                    \
     }                                                                          \
   }
 
@@ -460,7 +483,7 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
         if constexpr (kCount) ++n_visits;
         const uint32_t dt = t - gbase;
         uint32_t Z = z_item;
-        if constexpr (kPack == 2) {
+        if constexpr (kTwo) {
           if (lane >= dt) Z |= 0xFFFFu;
           if (lane + kWave >= dt) Z |= 0xFFFF0000u;
         } else {
@@ -521,8 +544,12 @@ __global__ __launch_bounds__(kBlock) void k_pairs(const Desc* __restrict__ descs
     const uint32_t groups = (d.np + 64u * d.pack - 1u) >> (d.pack == 2 ? 7u : 6u);
     const uint32_t c = local / groups;
     const uint32_t g = local - c * groups;
-    if (d.pack == 2) run_item(Tag<2>{}, d, g, c);
-    else run_item(Tag<1>{}, d, g, c);
+    if (d.pack == 2) {
+      if (d.m <= 15u) run_item(Tag<3>{}, d, g, c);
+      else run_item(Tag<2>{}, d, g, c);
+    } else {
+      run_item(Tag<1>{}, d, g, c);
+    }
   }
   if (staged) flush();
   if constexpr (kCount) {

@@ -434,6 +434,19 @@ __device__ void pass_counts(const Entry& en, int pass, uint32_t T, uint32_t& nde
   }
 }
 
+// Entry order of plan pass 0: the same entries with the pattern lengths
+// taken longest first.  Work items are handed out in plan order; started
+// early, the longer buckets' items (more steps per visited text) leave a
+// shorter end to the launch (N = 50,000, k = 2: 0.361 -> 0.353 ms; no change
+// at 800,000, where the diagonal pass forms the end).
+__device__ __forceinline__ uint32_t longest_first(const PlanPart& part, uint32_t e, int k) {
+  const uint32_t span = part.cross ? (uint32_t)(2 * k + 1) : (uint32_t)(k + 1);
+  const uint32_t per_seg = 32u * span;
+  const uint32_t seg = e / per_seg, rem = e - seg * per_seg;
+  const uint32_t li = rem / span;
+  return seg * per_seg + (31u - li) * span + (rem - li * span);
+}
+
 __global__ __launch_bounds__(kPlanThreads) void k_plan(const PlanPart* __restrict__ parts, uint32_t n_parts,
                                                        PlanPart inline_part, int k, uint32_t T,
                                                        uint32_t pack_ok, Desc* __restrict__ descs,
@@ -456,7 +469,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(const PlanPart* __restric
         en.ndesc = 0;
         en.items = 0;
         en.pairs = 0;
-        if (e < n_entries) en = entry_shape(part, e, k, T, pack_ok);
+        if (e < n_entries) en = entry_shape(part, pass == 0 ? longest_first(part, e, k) : e, k, T, pack_ok);
         uint32_t nd;
         uint64_t ni;
         pass_counts(en, pass, T, nd, ni);
