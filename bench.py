@@ -525,6 +525,9 @@ def main():
         tn.tcrnet_autotune(ctx, seqs, k)
     peak_meas, peak_s = tn.tcrnet_valu_peak(ctx)
     log(f"measured VALU issue rate {peak_meas / 1e12:.2f} T lane-instr/s ({peak_s * 1e3:.1f} ms probe)")
+    form_rates = tn.tcrnet_valu_rates(ctx)
+    log("issue rate by form (T lane-instr/s): " +
+        ", ".join(f"{kk} {v / 1e12:.1f}" for kk, v in form_rates.items()))
     step_s, E, infos = device_build(tn, torch, seqs, k, args.steps, args.warmup, ctx)
     pk_ms = float(np.mean([i["pair_kernel_ms"] for i in infos]))
     assert all(i["evaluated_pairs"] == ev_pairs for i in infos)
@@ -538,6 +541,12 @@ def main():
     rl["traffic_unit"] = "B per launch"
     rl["peak_measured"] = peak_meas / 1e12
     rl["frac_of_measured"] = rl["achieved"] * 1e12 / peak_meas
+    # per instruction form, in units of one wave64 instruction per SIMD per
+    # 4 clocks (39.3 T lane-instr/s): plain 32-bit logic/adds issue near 1.45,
+    # packed, 3-operand, min, shift, popcount and compare forms near 0.95
+    single = PEAK_LANE_OPS / 2
+    rl["issue_rates"] = {kk: round(v / single, 3) for kk, v in form_rates.items()}
+    rl["issue_rates_unit"] = "x one wave64 instruction per SIMD per 4 clocks"
     # the CPU work model of the same walk (bench_model.json), where it was
     # computed at this schedule
     model = load_model("paper_n800000_k1")

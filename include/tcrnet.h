@@ -268,6 +268,23 @@ TCRNET_API int32_t tcrnet_autotune_load(tcrnet_ctx* ctx, const char* path, uint3
  * TCRNET_EDEVICE. */
 TCRNET_API int32_t tcrnet_valu_peak(tcrnet_ctx* ctx, double* lane_instr_per_s, double* seconds);
 
+/* Measured issue rate of each of a fixed list of 32-bit VALU instruction
+ * forms, in lane-instructions per second, the same way as tcrnet_valu_peak
+ * (eight waves per SIMD, eight independent chains a wave, one form at a
+ * time): the forms the bit-vector step, its miss-word update and its within-k
+ * tests compile to (v_xor_b32, v_add_u32, v_and_b32, v_bitop3_b32,
+ * v_pk_add_u16, v_add3_u32, v_or3_b32, v_min_u32, v_min_u32 with an SDWA
+ * operand, v_lshlrev_b32, v_bcnt_u32_b32, v_cmp_eq_u32 into VCC).  They price
+ * the pair kernel's instruction mix: on gfx950 some forms issue at about twice
+ * the rate of others.  rates[i] receives form i, named by
+ * tcrnet_valu_form_name(i) (NULL past the last form); *n_forms receives the
+ * number of forms.  Runs about 50 ms of kernels on the context's stream and
+ * allocates a 2 MB scratch buffer.  Errors: TCRNET_EINVAL (NULL ctx or
+ * n_forms, or capacity below the number of forms: *n_forms is still set),
+ * TCRNET_EDEVICE. */
+TCRNET_API const char* tcrnet_valu_form_name(uint32_t i);
+TCRNET_API int32_t tcrnet_valu_rates(tcrnet_ctx* ctx, double* rates, uint32_t capacity, uint32_t* n_forms);
+
 /* ------------------------------------------------------------------ serving
  * A resident repertoire on the device (sorted into length buckets), with its
  * degree array at threshold k_index.  Query batches compare new sequences

@@ -97,6 +97,8 @@ _SIGS = [
     ("tcrnet_autotune_save", _I32, [_P, ctypes.c_char_p]),
     ("tcrnet_autotune_load", _I32, [_P, ctypes.c_char_p, _U32P]),
     ("tcrnet_valu_peak", _I32, [_P, ctypes.POINTER(ctypes.c_double), ctypes.POINTER(ctypes.c_double)]),
+    ("tcrnet_valu_form_name", ctypes.c_char_p, [ctypes.c_uint32]),
+    ("tcrnet_valu_rates", _I32, [_P, ctypes.POINTER(ctypes.c_double), ctypes.c_uint32, _U32P]),
     ("tcrnet_index_create", _I32, [_P, ctypes.POINTER(tcrnet_seqs), _I32, _PP]),
     ("tcrnet_index_size", _I32, [_P, _U32P]),
     ("tcrnet_index_degree", _I32, [_P, _PP, _U32P]),
@@ -371,6 +373,15 @@ def tcrnet_valu_peak(ctx: Context) -> tuple[float, float]:
     rate, sec = ctypes.c_double(), ctypes.c_double()
     _check(_lib.tcrnet_valu_peak(ctx.handle, ctypes.byref(rate), ctypes.byref(sec)))
     return rate.value, sec.value
+
+
+def tcrnet_valu_rates(ctx: Context) -> dict:
+    """{instruction form: measured lane-instructions per second}."""
+    n = ctypes.c_uint32(0)
+    _lib.tcrnet_valu_rates(ctx.handle, None, 0, ctypes.byref(n))  # asks for the count (EINVAL)
+    rates = (ctypes.c_double * n.value)()
+    _check(_lib.tcrnet_valu_rates(ctx.handle, rates, n.value, ctypes.byref(n)))
+    return {_lib.tcrnet_valu_form_name(i).decode(): rates[i] for i in range(n.value)}
 
 
 def version() -> str:

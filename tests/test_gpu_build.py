@@ -294,6 +294,16 @@ def test_valu_peak_probe(tn, ctx):
     assert 0.5 * 256 * 64 * 2.4e9 < rate < 1.05 * 256 * 128 * 2.4e9
 
 
+def test_valu_rate_probe(tn, ctx):
+    """Every instruction form gets a positive rate; the plain xor form runs at
+    the rate the peak probe measures (same chains, same grid)."""
+    rates = tn.tcrnet_valu_rates(ctx)
+    assert len(rates) == 12 and "v_pk_add_u16" in rates and "v_cmp_eq_u32" in rates
+    assert all(v > 1e12 for v in rates.values())
+    peak, _ = tn.tcrnet_valu_peak(ctx)
+    assert 0.7 < rates["v_xor_b32"] / peak < 1.3
+
+
 def test_injected_allocation_failures_are_clean(tn, orc):
     """Every device or pinned allocation of a build failing in turn: the call
     returns TCRNET_ENOMEM with no result, and the next call on the same
