@@ -477,6 +477,9 @@ def main():
                          "(HBM counter calibration); the run's schedule and work go to DIR/run.json")
     ap.add_argument("--calib-copy-mib", type=int, default=256)
     ap.add_argument("--ingest-counters", metavar="DIR", default=None)
+    ap.add_argument("--batch-only", action="store_true",
+                    help="profiling aid: tune the batched form (256 repertoires), then run --steps "
+                         "batched launches and print their timings; no bench line")
     args = ap.parse_args()
     if args.ingest_counters:
         ingest_counters(args.ingest_counters)
@@ -493,6 +496,22 @@ def main():
 
     tn.load_library()
     log(f"library {tn.version()}, device {torch.cuda.get_device_name(0)}")
+    if args.batch_only:
+        reps = synth.batch()
+        with tn.Context(0) as bctx:
+            tn.tcrnet_autotune_batch(bctx, reps, 1)
+            tn.tcrnet_build_batch(bctx, reps, 1)  # warm-up (captures the graph)
+            ms = []
+            for _ in range(args.steps):
+                t0 = time.perf_counter()
+                tn.tcrnet_build_batch(bctx, reps, 1)
+                ms.append((time.perf_counter() - t0) * 1e3)
+            info = bctx.last_info()
+        print(json.dumps({"batch_only": True, "repertoires": len(reps), "host_ms": ms,
+                          "device_ms": info["build_ms"],
+                          "schedule": {kk: info[kk] for kk in ("texts_per_item", "waves_per_simd", "peq_lds",
+                                                               "pack", "tuned")}}))
+        return
 
     k = 1
     seqs = synth.paper_scale()

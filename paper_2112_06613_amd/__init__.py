@@ -198,27 +198,52 @@ def _info_dict(inf: tcrnet_build_info) -> dict:
     return {f: getattr(inf, f) for f, _ in tcrnet_build_info._fields_}
 
 
+class _GraphOwner:
+    """Holds a tcrnet_graph until every array viewing its memory is gone."""
+    __slots__ = ("g",)
+
+    def __init__(self, g):
+        self.g = g
+
+    def __del__(self):
+        try:
+            if self.g and _lib is not None:
+                _lib.tcrnet_graph_free(self.g)
+        except Exception:  # interpreter shutdown
+            pass
+        self.g = None
+
+
+def _view(ptr, ctype, count: int, dtype, owner) -> np.ndarray:
+    """A numpy array over count elements of library-owned memory at ptr (no
+    copy); the memory lives as long as the array does."""
+    if not count or not ptr:
+        return np.zeros(0, dtype=dtype)
+    buf = (ctype * count).from_address(ptr)
+    buf._owner = owner
+    return np.frombuffer(buf, dtype=dtype)
+
+
 def _take_graph(g) -> Graph:
+    """Graph over the library's result: the arrays view its memory (no
+    copies: a batched build returns hundreds of graphs), which is freed when
+    the last of them is collected."""
+    owner = _GraphOwner(g)
     p = ctypes.c_void_p()
     ne = ctypes.c_uint64()
     _check(_lib.tcrnet_graph_edges(g, ctypes.byref(p), ctypes.byref(ne)))
-    E = ne.value
-    pairs = (np.ctypeslib.as_array(ctypes.cast(p, ctypes.POINTER(ctypes.c_uint32)), shape=(2 * E,)).copy()
-             if E else np.zeros(0, dtype=np.uint32))
+    pairs = _view(p.value, ctypes.c_uint32, 2 * ne.value, np.uint32, owner)
     d = ctypes.c_void_p()
     nn = ctypes.c_uint32()
     _check(_lib.tcrnet_graph_degree(g, ctypes.byref(d), ctypes.byref(nn)))
-    deg = (np.ctypeslib.as_array(ctypes.cast(d, ctypes.POINTER(ctypes.c_int32)), shape=(nn.value,)).copy()
-           if nn.value else np.zeros(0, dtype=np.int32))
+    deg = _view(d.value, ctypes.c_int32, nn.value, np.int32, owner)
     inf = tcrnet_build_info()
     _check(_lib.tcrnet_graph_info(g, ctypes.byref(inf)))
     dist = None
     dp = ctypes.c_void_p()
     dn = ctypes.c_uint64()
     if _lib.tcrnet_graph_distances(g, ctypes.byref(dp), ctypes.byref(dn)) == TCRNET_OK:
-        dist = (np.ctypeslib.as_array(ctypes.cast(dp, ctypes.POINTER(ctypes.c_uint8)), shape=(dn.value,)).copy()
-                if dn.value else np.zeros(0, dtype=np.uint8))
-    _lib.tcrnet_graph_free(g)
+        dist = _view(dp.value, ctypes.c_uint8, dn.value, np.uint8, owner)
     return Graph(pairs.reshape(-1, 2), deg, _info_dict(inf), dist)
 
 

@@ -384,33 +384,43 @@ int32_t tcrnet_build_batch(tcrnet_ctx* ctx, const tcrnet_seqs* reps, uint32_t n_
   uint64_t E = 0;
   if ((rc = batch_launch(ctx, bi, k, sched, &E, &info))) return rc;
   // split by repertoire: edges are sorted by global (i, j), so each
-  // repertoire's edges are one contiguous run
+  // repertoire's edges are one contiguous run, found by binary search; the
+  // results come back into pinned staging and are split on a few threads
   const uint32_t n = bi.n;
   const std::vector<uint32_t>& seg = bi.seg;
-  std::vector<uint32_t> all(2 * E);
-  std::vector<int32_t> deg(n);
   hipError_t e;
-  if (E) (void)hipMemcpyAsync(all.data(), ctx->out_pairs.p, E * 8, hipMemcpyDeviceToHost, ctx->stream);
-  if (n) (void)hipMemcpyAsync(deg.data(), ctx->out_deg.p, (uint64_t)n * 4, hipMemcpyDeviceToHost, ctx->stream);
+  const uint64_t deg_at = E * 8;
+  if ((e = ctx->batch_out.ensure(deg_at + (uint64_t)(n ? n : 1) * 4)) != hipSuccess)
+    return hip_error(e, "pinned result staging");
+  uint32_t* all = ctx->batch_out.as<uint32_t>();
+  int32_t* deg = reinterpret_cast<int32_t*>(ctx->batch_out.as<char>() + deg_at);
+  if (E) (void)hipMemcpyAsync(all, ctx->out_pairs.p, E * 8, hipMemcpyDeviceToHost, ctx->stream);
+  if (n) (void)hipMemcpyAsync(deg, ctx->out_deg.p, (uint64_t)n * 4, hipMemcpyDeviceToHost, ctx->stream);
   if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return hip_error(e, "result copy");
+  std::vector<uint64_t> first(n_reps + 1);
+  host_parallel(n_reps + 1, [&](uint32_t r) {
+    uint64_t lo = 0, hi = E;  // first edge whose smaller id is >= seg[r]
+    while (lo < hi) {
+      const uint64_t mid = (lo + hi) / 2;
+      if (all[2 * mid] < seg[r]) lo = mid + 1; else hi = mid;
+    }
+    first[r] = lo;
+  });
   std::vector<tcrnet_graph*> made(n_reps, nullptr);
-  uint64_t pos = 0;
-  for (uint32_t r = 0; r < n_reps; ++r) {
+  host_parallel(n_reps, [&](uint32_t r) {
     tcrnet_graph* g = new tcrnet_graph();
     const uint32_t b = seg[r], en = seg[r + 1];
     g->n = en - b;
-    g->deg.assign(deg.begin() + b, deg.begin() + en);
-    uint64_t q = pos;
-    while (q < E && all[2 * q] < en) ++q;
-    g->pairs.resize(2 * (q - pos));
-    for (uint64_t x = pos; x < q; ++x) {
-      g->pairs[2 * (x - pos)] = all[2 * x] - b;
-      g->pairs[2 * (x - pos) + 1] = all[2 * x + 1] - b;
+    g->deg.assign(deg + b, deg + en);
+    const uint64_t p0 = first[r], p1 = first[r + 1];
+    g->pairs.resize(2 * (p1 - p0));
+    for (uint64_t x = p0; x < p1; ++x) {
+      g->pairs[2 * (x - p0)] = all[2 * x] - b;
+      g->pairs[2 * (x - p0) + 1] = all[2 * x + 1] - b;
     }
-    pos = q;
     g->info = info;
     made[r] = g;
-  }
+  });
   for (uint32_t r = 0; r < n_reps; ++r) outs[r] = made[r];
   ctx->last = info;
   return TCRNET_OK;
@@ -438,37 +448,41 @@ int32_t batch_upload(tcrnet_ctx* ctx, const tcrnet_seqs* reps, uint32_t n_reps, 
   const uint32_t n = (uint32_t)total;
   bi->n = n;
   bi->n_reps = n_reps;
-  std::vector<uint64_t> off(n + 1);
-  std::vector<char>& hdata = ctx->batch_host;
-  hdata.resize(bytes ? bytes : 1);
-  {
-    uint64_t pos = 0;
-    uint32_t i = 0;
-    for (uint32_t r = 0; r < n_reps; ++r) {
-      const tcrnet_seqs& s = reps[r];
-      if (!s.n) continue;
-      const uint64_t b0 = s.offsets[0], nb = s.offsets[s.n] - b0;
-      memcpy(hdata.data() + pos, s.data + b0, nb);
-      for (uint32_t q = 0; q < s.n; ++q) off[i++] = pos + (s.offsets[q] - b0);
-      pos += nb;
-    }
-    off[n] = pos;
-  }
+  // characters then 8-aligned offsets, in pinned staging, filled on a few
+  // threads (one repertoire at a time each)
+  std::vector<uint64_t> boff(n_reps + 1, 0);
+  for (uint32_t r = 0; r < n_reps; ++r)
+    boff[r + 1] = boff[r] + (reps[r].n ? reps[r].offsets[reps[r].n] - reps[r].offsets[0] : 0);
+  const uint64_t off_at = (bytes + 7) & ~7ull;
+  if (hipError_t pe = ctx->batch_in.ensure(off_at + (uint64_t)(n + 1) * 8); pe != hipSuccess)
+    return hip_error(pe, "pinned input staging");
+  char* hdata = ctx->batch_in.as<char>();
+  uint64_t* off = reinterpret_cast<uint64_t*>(hdata + off_at);
+  host_parallel(n_reps, [&](uint32_t r) {
+    const tcrnet_seqs& s = reps[r];
+    if (!s.n) return;
+    const uint64_t b0 = s.offsets[0], pos = boff[r];
+    memcpy(hdata + pos, s.data + b0, boff[r + 1] - pos);
+    uint64_t* o = off + seg[r];
+    for (uint32_t q = 0; q < s.n; ++q) o[q] = pos + (s.offsets[q] - b0);
+  });
+  off[n] = bytes;
   hipError_t e;
   if ((e = ctx->in_data.ensure(bytes ? bytes : 1)) != hipSuccess) return hip_error(e, "input allocation");
   if ((e = ctx->in_off.ensure((uint64_t)(n + 1) * 8)) != hipSuccess) return hip_error(e, "input allocation");
   if ((e = ctx->in_seg.ensure((uint64_t)(n_reps + 1) * 4)) != hipSuccess) return hip_error(e, "input allocation");
   if ((e = ctx->out_deg.ensure((uint64_t)(n ? n : 1) * 4)) != hipSuccess) return hip_error(e, "output allocation");
-  if (bytes && (e = hipMemcpyAsync(ctx->in_data.p, hdata.data(), bytes, hipMemcpyHostToDevice, ctx->stream)) !=
+  if (bytes && (e = hipMemcpyAsync(ctx->in_data.p, hdata, bytes, hipMemcpyHostToDevice, ctx->stream)) !=
                    hipSuccess)
     return hip_error(e, "input copy");
-  if ((e = hipMemcpyAsync(ctx->in_off.p, off.data(), (uint64_t)(n + 1) * 8, hipMemcpyHostToDevice, ctx->stream)) !=
+  if ((e = hipMemcpyAsync(ctx->in_off.p, off, (uint64_t)(n + 1) * 8, hipMemcpyHostToDevice, ctx->stream)) !=
       hipSuccess)
     return hip_error(e, "input copy");
   if ((e = hipMemcpyAsync(ctx->in_seg.p, seg.data(), (uint64_t)(n_reps + 1) * 4, hipMemcpyHostToDevice,
                           ctx->stream)) != hipSuccess)
     return hip_error(e, "input copy");
-  // the host vectors are read by the copies above: wait before they go
+  // the staging buffers and the segment table are read by the copies above:
+  // wait before they can be reused or go
   if ((e = hipStreamSynchronize(ctx->stream)) != hipSuccess) return hip_error(e, "input copy");
   return TCRNET_OK;
 }

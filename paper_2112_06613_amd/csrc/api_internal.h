@@ -71,7 +71,7 @@ struct tcrnet_ctx {
   hipGraphExec_t batch_exec = nullptr;
   tcr::BatchKey batch_key;
   uint64_t batch_captures = 0;  // graphs captured so far (diagnostic)
-  std::vector<char> batch_host;
+  tcr::Pinned batch_in, batch_out;  // batched build: staging of inputs and results
 };
 
 namespace tcr {

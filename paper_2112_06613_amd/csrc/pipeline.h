@@ -1,8 +1,12 @@
 // Host-side orchestration shared by the build, batch and serving entry points.
 #pragma once
+#include <algorithm>
+#include <atomic>
 #include <cstdarg>
 #include <cstddef>
 #include <string>
+#include <thread>
+#include <vector>
 
 #include "kernels.h"
 
@@ -14,6 +18,54 @@ namespace tcr {
 hipError_t dev_malloc(void** p, size_t bytes);
 hipError_t host_malloc(void** p, size_t bytes);
 void arm_alloc_failure(int64_t after);  // -1: disarm
+
+// Runs f(i) for every i in [0, n) on up to 8 host threads that take indices
+// one at a time (the items of a batch differ in size).
+template <class F>
+void host_parallel(uint32_t n, F&& f) {
+  const unsigned hc = std::thread::hardware_concurrency();
+  const uint32_t nt = std::min<uint32_t>(n, std::min(8u, hc ? hc : 1u));
+  if (nt <= 1) {
+    for (uint32_t i = 0; i < n; ++i) f(i);
+    return;
+  }
+  std::atomic<uint32_t> next{0};
+  auto worker = [&]() {
+    for (uint32_t i = next.fetch_add(1); i < n; i = next.fetch_add(1)) f(i);
+  };
+  std::vector<std::thread> pool;
+  pool.reserve(nt - 1);
+  for (uint32_t t = 1; t < nt; ++t) pool.emplace_back(worker);
+  worker();
+  for (std::thread& t : pool) t.join();
+}
+
+// Page-locked host staging buffer, grow-only (copies from and to it run as
+// direct DMA; freeing one synchronises the device, so it only grows).
+struct Pinned {
+  void* p = nullptr;
+  size_t cap = 0;
+  Pinned() = default;
+  Pinned(const Pinned&) = delete;
+  Pinned& operator=(const Pinned&) = delete;
+  ~Pinned() { release(); }
+  void release() {
+    if (p) (void)hipHostFree(p);
+    p = nullptr;
+    cap = 0;
+  }
+  hipError_t ensure(size_t bytes) {
+    if (bytes <= cap && p) return hipSuccess;
+    release();
+    size_t nb = bytes < 4096 ? 4096 : bytes + bytes / 4;
+    hipError_t e = host_malloc(&p, nb);
+    if (e == hipSuccess) cap = nb;
+    else p = nullptr;
+    return e;
+  }
+  template <class T>
+  T* as() const { return static_cast<T*>(p); }
+};
 
 // Grow-only device buffer, or a borrowed view of memory the buffer does not
 // own (never freed, never grown).

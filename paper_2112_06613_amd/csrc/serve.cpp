@@ -154,29 +154,6 @@ struct Request {
   tcrnet_result* res = nullptr;
 };
 
-// Page-locked host staging buffer.
-struct Pinned {
-  void* p = nullptr;
-  size_t cap = 0;
-  ~Pinned() { release(); }
-  void release() {
-    if (p) (void)hipHostFree(p);
-    p = nullptr;
-    cap = 0;
-  }
-  hipError_t ensure(size_t bytes) {
-    if (bytes <= cap && p) return hipSuccess;
-    release();
-    size_t nb = bytes < 4096 ? 4096 : bytes + bytes / 4;
-    hipError_t e = host_malloc(&p, nb);
-    if (e == hipSuccess) cap = nb;
-    else p = nullptr;
-    return e;
-  }
-  template <class T>
-  T* as() const { return static_cast<T*>(p); }
-};
-
 struct Slot {
   hipStream_t st = nullptr;
   Pipeline pl;
