@@ -82,7 +82,7 @@ typedef struct {
 typedef struct {
   uint32_t texts_per_item;  /* texts per work item of the pair kernel
                                (0: autotuned table / about N/195 rounded
-                               down to a power of two in 512..16384, N the
+                               down to a power of two in 256..16384, N the
                                sequences of the launch; 1024 for a serving
                                index) */
   uint32_t waves_per_simd;  /* resident waves per SIMD of the persistent
@@ -219,7 +219,7 @@ TCRNET_API void tcrnet_graph_free(tcrnet_graph* g);
 /* --------------------------------------------------------------- autotune
  * Time candidate pair-kernel schedules and keep the fastest in the context
  * for later launches of the same form, size class (bits of the sequence
- * count) and k.  Candidates: texts per work item 512 .. 16384 (powers of
+ * count) and k.  Candidates: texts per work item 256 .. 16384 (powers of
  * two) x resident waves per SIMD {4, 6, 8} x pattern masks in VGPRs or LDS x
  * two patterns per lane on or off (off only, with TCRNET_F_NO_PACK).  Each
  * candidate is timed as the device time of its whole launch sequence, the

@@ -107,11 +107,14 @@ struct DevBuf {
 constexpr uint32_t kPairWavesPerSimd = 6;
 
 // Default texts per work item for a launch over n sequences: about n / 195,
-// rounded down to a power of two in [512, 16384] (measured best at 50,000 to
-// 800,000 sequences: 512 up to 100,000, 1,024 at 200,000-300,000, 2,048 at
-// 400,000, 4,096 at 800,000).
+// rounded down to a power of two in [256, 16384] (measured best at 50,000 to
+// 800,000 sequences: 256 at 50,000, 512 at 100,000, 1,024 at
+// 200,000-300,000, 2,048 at 400,000, 4,096 at 800,000; at 50,000 the launch
+// lasts as long as its heaviest items, and 256 texts shorten them more than
+// the extra items cost: 0.196 -> 0.172 ms at k = 1, 0.327 -> 0.304 at k = 2,
+// while 128 and 64 are slower again).
 inline uint32_t default_texts_per_item(uint64_t n) {
-  uint32_t t = 512;
+  uint32_t t = 256;
   while (t < 16384 && (uint64_t)(2 * t) * 195 <= n) t *= 2;
   return t;
 }

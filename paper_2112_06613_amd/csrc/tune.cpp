@@ -22,7 +22,7 @@ using namespace tcr;
 
 namespace {
 
-const uint32_t kTs[] = {512, 1024, 2048, 4096, 8192, 16384};
+const uint32_t kTs[] = {256, 512, 1024, 2048, 4096, 8192, 16384};
 const uint32_t kWs[] = {4, 6, 8};
 
 struct Candidate {

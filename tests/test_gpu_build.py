@@ -52,8 +52,8 @@ def test_full_oracle_ragged_20000_k2(tn, ctx, orc):
 def test_medium_k1_against_closed_form(tn, ctx, orc):
     s = synth.medium()
     g = tn.tcrnet_build(ctx, s, 1)
-    info = ctx.last_info()  # the defaults at 50,000 sequences: masks in VGPRs, 512 texts per item
-    assert info["peq_lds"] == 0 and info["texts_per_item"] == 512
+    info = ctx.last_info()  # the defaults at 50,000 sequences: masks in VGPRs, 256 texts per item
+    assert info["peq_lds"] == 0 and info["texts_per_item"] == 256
     e, d = orc.k1_build(s)
     _eq(g, e, d)
 

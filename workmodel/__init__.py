@@ -111,9 +111,9 @@ OUT = os.path.join(ROOT, "bench_model.json")
 # (generator, k, texts per work item: the library's default for the size,
 # about n / 195 rounded down to a power of two in 512..16384)
 WORKLOADS = {
-    "small_n2000_k1": (synth.small, 1, 512),
-    "medium_n50000_k1": (synth.medium, 1, 512),
-    "medium_n50000_k2": (synth.medium, 2, 512),
+    "small_n2000_k1": (synth.small, 1, 256),
+    "medium_n50000_k1": (synth.medium, 1, 256),
+    "medium_n50000_k2": (synth.medium, 2, 256),
     "paper_n800000_k1": (synth.paper_scale, 1, 4096),
 }
 
