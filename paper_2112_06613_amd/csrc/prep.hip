@@ -243,6 +243,7 @@ __global__ void k_gather(const SeqRec* __restrict__ rec, const uint32_t* __restr
 //               patterns (for equal lengths the set with fewer sequences
 //               when it has at least 64, else the other).
 constexpr int kPlanThreads = 1024;
+constexpr uint32_t kPlanPer = 4;  // entries per thread in a planning round
 
 __device__ uint32_t part_entries(const PlanPart& p, int k) {
   return p.cross ? 32u * (uint32_t)(2 * k + 1) : p.a.n_seg * 32u * (uint32_t)(k + 1);
@@ -447,6 +448,58 @@ __device__ __forceinline__ uint32_t longest_first(const PlanPart& part, uint32_t
   return seg * per_seg + (31u - li) * span + (rem - li * span);
 }
 
+// Descriptors of entry en in plan pass `pass` (nd of them, ni items) at
+// descriptor position dpos and item position ipos, unless they would run
+// past max_desc (the plan then reports an overflow).
+__device__ void write_entry(const Entry& en, int pass, uint32_t nd, uint64_t ni, uint64_t dpos, uint64_t ipos,
+                            uint32_t Td, uint32_t T, uint32_t max_desc, Desc* __restrict__ descs,
+                            uint64_t* __restrict__ item_base) {
+  if (dpos + nd <= max_desc) {
+    Desc d;
+    d.prec = en.prec;
+    d.ppeq = en.ppeq;
+    d.trec = en.trec;
+    d.twalk = en.twalk;
+    d.tw_len = en.tw_len;
+    d.m = en.m;
+    d.n = en.n;
+    d.tri = en.tri;
+    d.pack = en.pack;
+    const uint32_t G = 64u * en.pack;
+    if (!en.tri) {
+      d.p0 = en.p0; d.np = en.np; d.t0 = en.t0; d.nt = en.nt;
+      d.T = T;
+      d.chunks = (en.nt + T - 1) / T;
+      d.item_base = ipos;
+      d.items = ni;
+      descs[dpos] = d;
+      item_base[dpos] = ipos;
+    } else {
+      uint64_t ib = ipos;
+      uint32_t q = 0;
+      const TriChunks tc = tri_shape(en.np, T, Td);
+      for (uint32_t bk = 0; bk < en.ndesc; ++bk) {
+        const uint32_t rows = min(T, en.np - bk * T);
+        const uint32_t cols = en.np - bk * T;
+        d.p0 = en.p0 + bk * T; d.np = rows;
+        if (pass == 0) {
+          if (cols <= T) continue;
+          d.t0 = en.p0 + bk * T + T; d.nt = cols - T; d.T = T;
+        } else {
+          d.t0 = en.p0 + bk * T; d.nt = min(cols, T); d.T = Td;
+        }
+        d.chunks = tri_chunks(tc, en.np, bk, pass, T);
+        d.item_base = ib;
+        d.items = (uint64_t)((rows + G - 1) >> (en.pack == 2 ? 7u : 6u)) * d.chunks;
+        descs[dpos + q] = d;
+        item_base[dpos + q] = ib;
+        ib += d.items;
+        ++q;
+      }
+    }
+  }
+}
+
 __global__ __launch_bounds__(kPlanThreads) void k_plan(const PlanPart* __restrict__ parts, uint32_t n_parts,
                                                        PlanPart inline_part, int k, uint32_t T,
                                                        uint32_t pack_ok, Desc* __restrict__ descs,
@@ -463,63 +516,46 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(const PlanPart* __restric
     for (uint32_t pi = 0; pi < n_parts; ++pi) {
       const PlanPart part = parts ? parts[pi] : inline_part;
       const uint32_t n_entries = part_entries(part, k);
-      for (uint32_t e0 = 0; e0 < n_entries; e0 += kPlanThreads) {
-        const uint32_t e = e0 + threadIdx.x;
-        Entry en;
-        en.ndesc = 0;
-        en.items = 0;
-        en.pairs = 0;
-        if (e < n_entries) en = entry_shape(part, pass == 0 ? longest_first(part, e, k) : e, k, T, pack_ok);
-        uint32_t nd;
-        uint64_t ni;
-        pass_counts(en, pass, T, nd, ni);
-        uint64_t tot_d, tot_i, tot_p;
-        const uint64_t dpos = run_desc + block_excl_scan_u64(nd, sh, tot_d);
-        const uint64_t ipos = run_items + block_excl_scan_u64(ni, sh, tot_i);
-        block_excl_scan_u64(pass == 0 ? en.pairs : 0, sh, tot_p);
-        if (nd > 0 && dpos + nd <= max_desc) {
-          Desc d;
-          d.prec = en.prec;
-          d.ppeq = en.ppeq;
-          d.trec = en.trec;
-          d.twalk = en.twalk;
-          d.tw_len = en.tw_len;
-          d.m = en.m;
-          d.n = en.n;
-          d.tri = en.tri;
-          d.pack = en.pack;
-          const uint32_t G = 64u * en.pack;
-          if (!en.tri) {
-            d.p0 = en.p0; d.np = en.np; d.t0 = en.t0; d.nt = en.nt;
-            d.T = T;
-            d.chunks = (en.nt + T - 1) / T;
-            d.item_base = ipos;
-            d.items = ni;
-            descs[dpos] = d;
-            item_base[dpos] = ipos;
-          } else {
-            uint64_t ib = ipos;
-            uint32_t q = 0;
-            const TriChunks tc = tri_shape(en.np, T, Td);
-            for (uint32_t bk = 0; bk < en.ndesc; ++bk) {
-              const uint32_t rows = min(T, en.np - bk * T);
-              const uint32_t cols = en.np - bk * T;
-              d.p0 = en.p0 + bk * T; d.np = rows;
-              if (pass == 0) {
-                if (cols <= T) continue;
-                d.t0 = en.p0 + bk * T + T; d.nt = cols - T; d.T = T;
-              } else {
-                d.t0 = en.p0 + bk * T; d.nt = min(cols, T); d.T = Td;
-              }
-              d.chunks = tri_chunks(tc, en.np, bk, pass, T);
-              d.item_base = ib;
-              d.items = (uint64_t)((rows + G - 1) >> (en.pack == 2 ? 7u : 6u)) * d.chunks;
-              descs[dpos + q] = d;
-              item_base[dpos + q] = ib;
-              ib += d.items;
-              ++q;
-            }
+      // a round plans `per` consecutive entries per thread: their counts
+      // first, then one scan of each per-thread total over the block, then
+      // the descriptors (the entry shapes taken again), in entry order.  A
+      // part of many entries (a batch: 32 (k+1) per repertoire) takes
+      // kPlanPer per thread, which divides its rounds and scans by kPlanPer
+      // (256 repertoires: 229 -> 111 us); one round of a part that fits the
+      // block keeps one entry per thread, whose shapes then take their loads
+      // and loops side by side.
+      const uint32_t per = n_entries > (uint32_t)kPlanThreads ? kPlanPer : 1u;
+      for (uint32_t e0 = 0; e0 < n_entries; e0 += kPlanThreads * per) {
+        const uint32_t eb = e0 + threadIdx.x * per;
+        uint32_t nd_j[kPlanPer];
+        uint64_t ni_j[kPlanPer];
+        uint32_t td = 0;
+        uint64_t ti = 0, tp = 0;
+#pragma unroll
+        for (uint32_t j = 0; j < kPlanPer; ++j) {
+          nd_j[j] = 0;
+          ni_j[j] = 0;
+          if (j < per && eb + j < n_entries) {
+            const Entry en = entry_shape(part, pass == 0 ? longest_first(part, eb + j, k) : eb + j, k, T, pack_ok);
+            pass_counts(en, pass, T, nd_j[j], ni_j[j]);
+            if (pass == 0) tp += en.pairs;
           }
+          td += nd_j[j];
+          ti += ni_j[j];
+        }
+        uint64_t tot_d, tot_i, tot_p;
+        uint64_t dpos = run_desc + block_excl_scan_u64(td, sh, tot_d);
+        uint64_t ipos = run_items + block_excl_scan_u64(ti, sh, tot_i);
+        block_excl_scan_u64(tp, sh, tot_p);
+#pragma unroll
+        for (uint32_t j = 0; j < kPlanPer; ++j) {
+          const uint32_t nd = nd_j[j];
+          const uint64_t ni = ni_j[j];
+          if (nd > 0) write_entry(entry_shape(part, pass == 0 ? longest_first(part, eb + j, k) : eb + j, k, T,
+                                              pack_ok),
+                                  pass, nd, ni, dpos, ipos, Td, T, max_desc, descs, item_base);
+          dpos += nd;
+          ipos += ni;
         }
         run_desc += tot_d;
         run_items += tot_i;
