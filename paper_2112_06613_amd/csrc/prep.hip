@@ -357,18 +357,31 @@ __device__ Entry entry_shape(const PlanPart& part, uint32_t e, int k, uint32_t T
   return r;
 }
 
-__device__ uint64_t block_excl_scan_u64(uint64_t v, uint64_t* sh, uint64_t& total) {
+// Exclusive prefix sums over the block of three values at once (the
+// barriers of one scan serve all three), and their block totals.
+struct Scan3 {
+  uint64_t v[3];
+};
+__device__ Scan3 block_excl_scan3(Scan3 in, uint64_t (*sh)[kPlanThreads], Scan3& total) {
   const int t = threadIdx.x;
-  sh[t] = v;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) sh[q][t] = in.v[q];
   __syncthreads();
   for (int d = 1; d < kPlanThreads; d <<= 1) {
-    uint64_t x = t >= d ? sh[t - d] : 0;
+    uint64_t x[3];
+#pragma unroll
+    for (int q = 0; q < 3; ++q) x[q] = t >= d ? sh[q][t - d] : 0;
     __syncthreads();
-    sh[t] += x;
+#pragma unroll
+    for (int q = 0; q < 3; ++q) sh[q][t] += x[q];
     __syncthreads();
   }
-  total = sh[kPlanThreads - 1];
-  uint64_t r = sh[t] - v;
+  Scan3 r;
+#pragma unroll
+  for (int q = 0; q < 3; ++q) {
+    total.v[q] = sh[q][kPlanThreads - 1];
+    r.v[q] = sh[q][t] - in.v[q];
+  }
   __syncthreads();
   return r;
 }
@@ -505,7 +518,7 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(const PlanPart* __restric
                                                        uint32_t pack_ok, Desc* __restrict__ descs,
                                                        uint64_t* __restrict__ item_base, uint32_t max_desc,
                                                        Plan* plan) {
-  __shared__ uint64_t sh[kPlanThreads];
+  __shared__ uint64_t sh[3][kPlanThreads];
   if (!parts) {
     parts = nullptr;
     n_parts = 1;
@@ -543,10 +556,10 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(const PlanPart* __restric
           td += nd_j[j];
           ti += ni_j[j];
         }
-        uint64_t tot_d, tot_i, tot_p;
-        uint64_t dpos = run_desc + block_excl_scan_u64(td, sh, tot_d);
-        uint64_t ipos = run_items + block_excl_scan_u64(ti, sh, tot_i);
-        block_excl_scan_u64(tp, sh, tot_p);
+        Scan3 tot;
+        const Scan3 pre = block_excl_scan3(Scan3{{td, ti, tp}}, sh, tot);
+        uint64_t dpos = run_desc + pre.v[0];
+        uint64_t ipos = run_items + pre.v[1];
 #pragma unroll
         for (uint32_t j = 0; j < kPlanPer; ++j) {
           const uint32_t nd = nd_j[j];
@@ -557,9 +570,9 @@ __global__ __launch_bounds__(kPlanThreads) void k_plan(const PlanPart* __restric
           dpos += nd;
           ipos += ni;
         }
-        run_desc += tot_d;
-        run_items += tot_i;
-        run_pairs += tot_p;
+        run_desc += tot.v[0];
+        run_items += tot.v[1];
+        run_pairs += tot.v[2];
       }
     }
   }
