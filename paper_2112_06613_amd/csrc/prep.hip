@@ -307,15 +307,7 @@ __device__ Entry entry_shape(const PlanPart& part, uint32_t e, int k, uint32_t T
       if (r.np < 2) return r;
       r.tri = 1;
       r.ndesc = (r.np - 1 + T - 1) / T;  // row blocks b with b*T <= np-2
-      // row block bk: ceil(rows / G) groups (G a power of two) times
-      // ceil((np - bk*T) / T) = C - bk chunks (no division in the loop:
-      // one thread plans a whole triangle)
-      const uint32_t gsh = r.pack == 2 ? 7u : 6u;
-      const uint32_t C = (r.np + T - 1) / T;
-      for (uint32_t bk = 0; bk < r.ndesc; ++bk) {
-        const uint32_t rows = min(T, r.np - bk * T);
-        r.items += (uint64_t)((rows + G - 1) >> gsh) * (C - bk);
-      }
+      // (a triangle's items are counted per plan pass, by pass_counts)
       r.pairs = (uint64_t)r.np * (r.np - 1) / 2;
     }
   } else {
