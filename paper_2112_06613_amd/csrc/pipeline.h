@@ -19,6 +19,15 @@ hipError_t dev_malloc(void** p, size_t bytes);
 hipError_t host_malloc(void** p, size_t bytes);
 void arm_alloc_failure(int64_t after);  // -1: disarm
 
+// Chunks of a host-side copy of `bytes` handed to host_parallel: one per MiB,
+// at most 32 (starting and joining its threads costs about 0.2 ms, more than
+// a copy of under a MiB takes on one thread).
+constexpr uint32_t kHostChunks = 32;
+inline uint32_t host_chunks(uint64_t bytes) {
+  const uint64_t c = bytes >> 20;
+  return c < 1 ? 1u : (c > kHostChunks ? kHostChunks : (uint32_t)c);
+}
+
 // Runs f(i) for every i in [0, n) on up to 8 host threads that take indices
 // one at a time (the items of a batch differ in size).
 template <class F>
