@@ -177,13 +177,24 @@ TCRNET_API int32_t tcrnet_build_weighted(tcrnet_ctx* ctx, const tcrnet_seqs* seq
 
 /* Many independent repertoires (each its own network, own 0-based ids) in
  * one launch sequence: one persistent pair kernel over all repertoires' work
- * items, captured in a HIP graph.  outs[r] receives repertoire r's graph. */
+ * items, captured in a HIP graph.  outs[r] receives repertoire r's graph;
+ * every graph's tcrnet_graph_info is that of the one batched launch. */
 TCRNET_API int32_t tcrnet_build_batch(tcrnet_ctx* ctx, const tcrnet_seqs* reps, uint32_t n_reps,
                                       int32_t k, tcrnet_graph** outs);
 
 /* Host views of a graph (valid until tcrnet_graph_free). */
 TCRNET_API int32_t tcrnet_graph_edges(const tcrnet_graph* g, const uint32_t** pairs, uint64_t* n_edges);
 TCRNET_API int32_t tcrnet_graph_degree(const tcrnet_graph* g, const int32_t** degree, uint32_t* n);
+/* The views of graphs[0 .. n) in one call, for callers that wrap the hundreds
+ * of graphs of a batched build: entry i of each output array (n entries
+ * each, caller-owned) is what tcrnet_graph_edges (pairs, n_edges),
+ * tcrnet_graph_degree (degree, n_nodes) and tcrnet_graph_distances (dist:
+ * NULL for a graph without distances) give graphs[i].  The views stay valid
+ * until that graph is freed.  Errors: TCRNET_EINVAL for a NULL array (with
+ * n > 0) or a NULL graph; outputs before the failing entry are filled. */
+TCRNET_API int32_t tcrnet_graphs_views(tcrnet_graph* const* graphs, uint32_t n, const uint32_t** pairs,
+                                       uint64_t* n_edges, const int32_t** degree, uint32_t* n_nodes,
+                                       const uint8_t** dist);
 /* Edge distances (E bytes, aligned with the edge list) of a weighted build;
    TCRNET_ESTATE for other graphs. */
 TCRNET_API int32_t tcrnet_graph_distances(const tcrnet_graph* g, const uint8_t** dist, uint64_t* n_edges);

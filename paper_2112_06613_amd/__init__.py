@@ -86,6 +86,7 @@ _SIGS = [
     ("tcrnet_build_batch", _I32, [_P, ctypes.POINTER(tcrnet_seqs), ctypes.c_uint32, _I32, _PP]),
     ("tcrnet_graph_edges", _I32, [_P, _PP, _U64P]),
     ("tcrnet_graph_degree", _I32, [_P, _PP, _U32P]),
+    ("tcrnet_graphs_views", _I32, [_P, ctypes.c_uint32, _P, _P, _P, _P, _P]),
     ("tcrnet_graph_info", _I32, [_P, ctypes.POINTER(tcrnet_build_info)]),
     ("tcrnet_ctx_last_info", _I32, [_P, ctypes.POINTER(tcrnet_build_info)]),
     ("tcrnet_graph_free", None, [_P]),
@@ -343,14 +344,45 @@ def tcrnet_build_device_noalloc(ctx: Context, d_chars, d_offsets, k: int, d_pair
 NOALLOC_SCRATCH_BYTES = 64 << 20  # TCRNET_NOALLOC_SCRATCH_BYTES
 
 
+# tcrnet_seqs as a numpy record (an array of them is filled column-wise:
+# hundreds of repertoires cost one assignment per field, not one per entry)
+_SEQS_DTYPE = np.dtype({"names": ["data", "offsets", "n"], "formats": ["<u8", "<u8", "<u4"],
+                        "offsets": [tcrnet_seqs.data.offset, tcrnet_seqs.offsets.offset, tcrnet_seqs.n.offset],
+                        "itemsize": ctypes.sizeof(tcrnet_seqs)})
+
+
 def tcrnet_build_batch(ctx: Context, reps, k: int) -> list[Graph]:
     conv = [_as_seqs(r) for r in reps]
-    arr = (tcrnet_seqs * max(1, len(conv)))()
-    for i, (c, o) in enumerate(conv):
-        arr[i] = _c_seqs(c, o)
-    outs = (ctypes.c_void_p * max(1, len(conv)))()
-    _check(_lib.tcrnet_build_batch(ctx.handle, arr, len(conv), k, outs))
-    return [_take_graph(ctypes.c_void_p(outs[i])) for i in range(len(conv))]
+    nr = len(conv)
+    desc = np.zeros(max(1, nr), dtype=_SEQS_DTYPE)
+    if nr:
+        desc["data"][:nr] = [c.__array_interface__["data"][0] for c, _ in conv]
+        desc["offsets"][:nr] = [o.__array_interface__["data"][0] for _, o in conv]
+        desc["n"][:nr] = [len(o) - 1 for _, o in conv]
+    outs = (ctypes.c_void_p * max(1, nr))()
+    _check(_lib.tcrnet_build_batch(ctx.handle, ctypes.cast(desc.ctypes.data, ctypes.POINTER(tcrnet_seqs)), nr, k,
+                                   outs))
+    if not nr:
+        return []
+    # every graph owns its arrays from here on; their views come in one call
+    owners = [_GraphOwner(ctypes.c_void_p(outs[i])) for i in range(nr)]
+    pp = np.zeros(nr, np.uint64)
+    ne = np.zeros(nr, np.uint64)
+    dp = np.zeros(nr, np.uint64)
+    nn = np.zeros(nr, np.uint32)
+    xp = np.zeros(nr, np.uint64)
+    _check(_lib.tcrnet_graphs_views(outs, nr, pp.ctypes.data, ne.ctypes.data, dp.ctypes.data, nn.ctypes.data,
+                                    xp.ctypes.data))
+    inf = tcrnet_build_info()
+    _check(_lib.tcrnet_graph_info(outs[0], ctypes.byref(inf)))
+    info = _info_dict(inf)  # the batched launch's, the same for every graph
+    graphs = []
+    for i in range(nr):
+        o = owners[i]
+        pairs = _view(int(pp[i]), ctypes.c_uint32, 2 * int(ne[i]), np.uint32, o).reshape(-1, 2)
+        deg = _view(int(dp[i]), ctypes.c_int32, int(nn[i]), np.int32, o)
+        graphs.append(Graph(pairs, deg, dict(info), None))
+    return graphs
 
 
 def tcrnet_autotune(ctx: Context, seqs, k: int) -> None:

@@ -424,6 +424,22 @@ int32_t tcrnet_ctx_last_info(const tcrnet_ctx* ctx, tcrnet_build_info* info) {
 
 void tcrnet_graph_free(tcrnet_graph* g) { delete g; }
 
+int32_t tcrnet_graphs_views(tcrnet_graph* const* graphs, uint32_t n, const uint32_t** pairs, uint64_t* n_edges,
+                            const int32_t** degree, uint32_t* n_nodes, const uint8_t** dist) {
+  if (n && (!graphs || !pairs || !n_edges || !degree || !n_nodes || !dist))
+    return set_error(TCRNET_EINVAL, "NULL argument");
+  for (uint32_t i = 0; i < n; ++i) {
+    const tcrnet_graph* g = graphs[i];
+    if (!g) return set_error(TCRNET_EINVAL, "graph %u is NULL", i);
+    pairs[i] = g->pairs.empty() ? nullptr : g->pairs.data();
+    n_edges[i] = g->pairs.size() / 2;
+    degree[i] = g->deg.empty() ? nullptr : g->deg.data();
+    n_nodes[i] = g->n;
+    dist[i] = g->dist.empty() || g->dist.size() != g->pairs.size() / 2 ? nullptr : g->dist.data();
+  }
+  return TCRNET_OK;
+}
+
 // ----------------------------------------------------------------- batch
 int32_t tcrnet_build_batch(tcrnet_ctx* ctx, const tcrnet_seqs* reps, uint32_t n_reps, int32_t k,
                            tcrnet_graph** outs) {

@@ -40,6 +40,13 @@ def test_host_only_calls():
     assert lib.tcrnet_ctx_create(0, None, None) == tn.TCRNET_EINVAL
     assert b"NULL" in lib.tcrnet_last_error()
     assert lib.tcrnet_build(None, None, 1, None) == tn.TCRNET_EINVAL
+    # bulk graph views: nothing to describe is fine, missing arrays or graphs are not
+    assert lib.tcrnet_graphs_views(None, 0, None, None, None, None, None) == tn.TCRNET_OK
+    assert lib.tcrnet_graphs_views(None, 1, None, None, None, None, None) == tn.TCRNET_EINVAL
+    slots = [ctypes.create_string_buffer(16) for _ in range(5)]
+    nulls = (ctypes.c_void_p * 1)()
+    assert lib.tcrnet_graphs_views(nulls, 1, *slots) == tn.TCRNET_EINVAL
+    assert b"graph 0 is NULL" in lib.tcrnet_last_error()
 
 
 def test_no_device_reports_edevice():
