@@ -86,7 +86,8 @@ typedef struct {
                                sequences of the launch; 512 for a serving
                                index) */
   uint32_t waves_per_simd;  /* resident waves per SIMD of the persistent
-                               pair kernel (0: 8) */
+                               pair kernel (0: autotuned table / 6, what
+                               the kernel's registers allow) */
   uint64_t edge_capacity;   /* initial edge buffer capacity in edges (0: sized
                                from N); too small only costs one re-run */
   uint64_t hbm_budget;      /* serving: bytes of device memory that admitted
