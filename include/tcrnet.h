@@ -192,7 +192,7 @@ TCRNET_API int32_t tcrnet_graph_degree(const tcrnet_graph* g, const int32_t** de
  * tcrnet_graph_degree (degree, n_nodes) and tcrnet_graph_distances (dist:
  * NULL for a graph without distances) give graphs[i].  The views stay valid
  * until that graph is freed.  Errors: TCRNET_EINVAL for a NULL array (with
- * n > 0) or a NULL graph; outputs before the failing entry are filled. */
+ * n > 0) or a NULL graph (then no output is written). */
 TCRNET_API int32_t tcrnet_graphs_views(tcrnet_graph* const* graphs, uint32_t n, const uint32_t** pairs,
                                        uint64_t* n_edges, const int32_t** degree, uint32_t* n_nodes,
                                        const uint8_t** dist);

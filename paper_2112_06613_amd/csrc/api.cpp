@@ -428,9 +428,10 @@ int32_t tcrnet_graphs_views(tcrnet_graph* const* graphs, uint32_t n, const uint3
                             const int32_t** degree, uint32_t* n_nodes, const uint8_t** dist) {
   if (n && (!graphs || !pairs || !n_edges || !degree || !n_nodes || !dist))
     return set_error(TCRNET_EINVAL, "NULL argument");
+  for (uint32_t i = 0; i < n; ++i)
+    if (!graphs[i]) return set_error(TCRNET_EINVAL, "graph %u is NULL", i);
   for (uint32_t i = 0; i < n; ++i) {
     const tcrnet_graph* g = graphs[i];
-    if (!g) return set_error(TCRNET_EINVAL, "graph %u is NULL", i);
     pairs[i] = g->pairs.empty() ? nullptr : g->pairs.data();
     n_edges[i] = g->pairs.size() / 2;
     degree[i] = g->deg.empty() ? nullptr : g->deg.data();
