@@ -171,8 +171,8 @@ TCRNET_API int32_t tcrnet_build_device_noalloc(tcrnet_ctx* ctx, const char* d_da
 /* Multi-threshold build: every pair with lev <= k_max, with its exact
  * distance (paper, Results, "LCC transition": networks for several l_max).
  * The network at any k <= k_max is the set of edges with distance <= k.
- * Degrees are those at k_max.  At most 2^29 sequences.  The distances are
- * read with tcrnet_graph_distances. */
+ * Degrees are those at k_max.  The distances are read with
+ * tcrnet_graph_distances. */
 TCRNET_API int32_t tcrnet_build_weighted(tcrnet_ctx* ctx, const tcrnet_seqs* seqs, int32_t k_max,
                                          tcrnet_graph** out);
 
