@@ -492,7 +492,7 @@ def main():
         ingest_counters(args.ingest_counters)
         return
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the network build runs on one GPU (asked for --gpus {args.gpus}); "
               "the path is not sharded across GPUs", file=sys.stderr)
         sys.exit(2)
 
