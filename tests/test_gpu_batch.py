@@ -33,6 +33,22 @@ def test_uneven_batch_matches_oracle(tn, ctx, orc):
             assert np.array_equal(g.degree, d)
 
 
+def test_many_small_repertoires_partial_plan_rounds(tn, ctx, orc):
+    # 70 repertoires plan 32 (k + 1) entries each, 4,480 at k = 1 and 6,720 at
+    # k = 2: more than the planning block has threads, so the planner hands
+    # them out four to a thread, in rounds of 4,096 entries whose last one is
+    # partial
+    sizes = [37 + (i * 53) % 400 for i in range(70)]
+    reps = [synth.repertoire(n, max(1, n // 8), 700 + i) for i, n in enumerate(sizes)]
+    for k in (1, 2):
+        gs = tn.tcrnet_build_batch(ctx, reps, k)
+        assert len(gs) == len(reps)
+        for r, g in zip(reps, gs):
+            e, d = orc.build(r, k)
+            assert np.array_equal(g.pairs, e)
+            assert np.array_equal(g.degree, d)
+
+
 def test_replayed_graph_gives_same_results(tn, ctx):
     reps = [synth.repertoire(n, n // 10, 900 + n) for n in (1200, 2500, 800)]
     a = tn.tcrnet_build_batch(ctx, reps, 1)
