@@ -65,6 +65,19 @@ def test_query_matches_oracle(tn, ctx, orc, rep, k):
     assert r.info["is_insert"] == 0 and r.info["snapshot_size"] == rep.n
 
 
+@pytest.mark.parametrize("k", [16, 31])
+def test_query_large_k_matches_oracle(tn, ctx, orc, rep, k):
+    # a query's cross part plans 32 (2k + 1) entries, here more than the
+    # planning block has threads: they go four to a thread; no packing (a
+    # masked half's 16 set miss bits would not exceed k)
+    q = synth.queries(40, T0, 7, 301 + k)
+    with tn.tcrnet_index_create(ctx, rep, 1) as idx:
+        r = tn.tcrnet_query(idx, q, k)
+    e, c = _query_ref(orc, rep, q, k)
+    assert np.array_equal(r.pairs, e)
+    assert np.array_equal(r.counts, c)
+
+
 def test_index_degrees_equal_plain_build(tn, ctx, orc, rep):
     with tn.tcrnet_index_create(ctx, rep, 1) as idx:
         assert idx.size() == rep.n
