@@ -83,8 +83,8 @@ typedef struct {
   uint32_t texts_per_item;  /* texts per work item of the pair kernel
                                (0: autotuned table / about N/195 rounded
                                down to a power of two in 256..16384, N the
-                               sequences of the launch; 512 for a serving
-                               index) */
+                               sequences of the launch, doubled at k <= 1
+                               from N = 150,000; 512 for a serving index) */
   uint32_t waves_per_simd;  /* resident waves per SIMD of the persistent
                                pair kernel (0: autotuned table / 6, what
                                the kernel's registers allow) */

@@ -97,7 +97,7 @@ Sched pick_sched(const tcrnet_ctx* ctx, uint64_t n, int k, int form) {
   // k = 2: 1.78 ms at 16,384 texts per item, 0.49 ms at 512).
   s.peq_lds = false;
   s.waves_per_simd = kPairWavesPerSimd;
-  s.texts_per_item = default_texts_per_item(n);
+  s.texts_per_item = default_texts_per_item(n, k);
   if (!(ctx->opts.flags & TCRNET_F_NO_AUTOTUNE)) {
     TuneKey key;
     key.form = form;

@@ -115,16 +115,20 @@ struct DevBuf {
 // Resident waves per SIMD of the pair kernel (its register count allows six).
 constexpr uint32_t kPairWavesPerSimd = 6;
 
-// Default texts per work item for a launch over n sequences: about n / 195,
-// rounded down to a power of two in [256, 16384] (measured best at 50,000 to
-// 800,000 sequences: 256 at 50,000, 512 at 100,000, 1,024 at
-// 200,000-300,000, 2,048 at 400,000, 4,096 at 800,000; at 50,000 the launch
-// lasts as long as its heaviest items, and 256 texts shorten them more than
-// the extra items cost: 0.196 -> 0.172 ms at k = 1, 0.327 -> 0.304 at k = 2,
-// while 128 and 64 are slower again).
-inline uint32_t default_texts_per_item(uint64_t n) {
+// Default texts per work item for a launch over n sequences at threshold k:
+// about n / 195, rounded down to a power of two in [256, 16384], and one
+// doubling more at k <= 1 from 150,000 sequences on.  Measured best: 256 at
+// 50,000 (the launch lasts as long as its heaviest items, and 256 texts
+// shorten them more than the extra items cost: 0.196 -> 0.172 ms at k = 1,
+// 0.327 -> 0.304 at k = 2, while 128 and 64 are slower again), 512 at
+// 100,000 (1,024: 0.230 -> 0.260 ms); at k = 1, 2,048 at 200,000 (0.427 ->
+// 0.424 ms against 1,024), 4,096 at 400,000 (0.739 -> 0.729 against 2,048)
+// and 8,192 at 800,000 (1.39 -> 1.30 ms against 4,096; 16,384: 1.33); at
+// k = 2, 800,000 keeps 4,096 (11.32 ms, 11.47 at 8,192).
+inline uint32_t default_texts_per_item(uint64_t n, int k) {
   uint32_t t = 256;
   while (t < 16384 && (uint64_t)(2 * t) * 195 <= n) t *= 2;
+  if (k <= 1 && n >= 150000 && t < 16384) t *= 2;
   return t;
 }
 

@@ -90,8 +90,8 @@ def test_medium_k2_sampled_rows_and_soundness(tn, ctx, orc):
 def test_paper_scale_k1_bit_exact(tn, ctx, orc):
     s = synth.paper_scale()
     g = tn.tcrnet_build(ctx, s, 1)
-    info = ctx.last_info()  # the defaults at this size: masks in VGPRs, 4,096 texts per item
-    assert info["peq_lds"] == 0 and info["texts_per_item"] == 4096
+    info = ctx.last_info()  # the defaults at this size and k: masks in VGPRs, 8,192 texts per item
+    assert info["peq_lds"] == 0 and info["texts_per_item"] == 8192
     e, d = orc.k1_build(s)
     _eq(g, e, d)
     # the same launch with the pattern masks in LDS

@@ -114,7 +114,7 @@ WORKLOADS = {
     "small_n2000_k1": (synth.small, 1, 256),
     "medium_n50000_k1": (synth.medium, 1, 256),
     "medium_n50000_k2": (synth.medium, 2, 256),
-    "paper_n800000_k1": (synth.paper_scale, 1, 4096),
+    "paper_n800000_k1": (synth.paper_scale, 1, 8192),
 }
 
 
