@@ -10,6 +10,12 @@
 
 namespace tcr {
 
+// The gather writes the walk arrays' residue codes from a record's first
+// word, which holds residues 0-5: the walk's sibling-loop depth cannot exceed
+// six without that changing (a depth of 7 gave wrong edges; 5 was slower,
+// 1.31 -> 1.43 ms at N = 800,000).
+static_assert(kWalkDepth <= 6, "walk codes come from SeqRec::w[0] (six residues)");
+
 namespace {
 thread_local std::string g_last_error;
 std::atomic<int64_t> g_fail_after{-1};  // successful allocations before an injected failure (-1: none)
